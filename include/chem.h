@@ -1,0 +1,211 @@
+/*
+ * chem.h -- C ABI of the per-cell chemistry library (libchem.so) for AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates, for every CFD cell independently, the chemical state y = (T, C_1..C_ns)
+ * of the ChemGen paper (arXiv 2510.10005, Section 3, eq. extracted_problem): NASA-7 species
+ * thermodynamics (Section 2.1, Table 1), the source term S(y) = (omega_T, omega_1..omega_ns) with
+ * Arrhenius, third-body and Troe/Lindemann falloff rates and reverse rates from equilibrium
+ * constants (Section 2.2), its analytic Jacobian (Section 3.2), and the implicit integration of
+ * dy/dt = S(y) over one operator-split step (backward Euler with Newton, Section 3.2; two-stage
+ * Rosenbrock, Appendix A.3), plus the discrete adjoint of the backward-Euler integration.
+ *
+ * Conventions shared by every call:
+ *  - Units are SI with kmol: T [K], C [kmol/m^3], p [Pa], time [s].
+ *  - Arrays named y, dydt, jac, T, p, Y, cp, h, s, g are DEVICE pointers to FP64 data laid out
+ *    structure-of-arrays with leading dimension ld >= n_cells: component k of cell c lives at
+ *    [k * ld + c].  State index 0 is T, index 1 + i is species i.  The Jacobian uses component
+ *    (i * n + j) for dS_i/dy_j with n = ns + 1.
+ *  - lnA (nullable) is a DEVICE array of nr FP64 values: ln of each reaction's (high-pressure)
+ *    Arrhenius prefactor in SI-kmol units.  For a falloff reaction the low-pressure prefactor
+ *    moves with it, so lnA_j scales k_f and k_r of reaction j alike.  NULL means the file's values.
+ *  - stream is a hipStream_t (NULL = the default stream).  Work is enqueued asynchronously on it;
+ *    argument errors are reported synchronously before anything is enqueued.
+ *  - The caller owns every array passed in.  The library owns mechanisms, compiled kernels,
+ *    tapes and its internal workspaces.  Calls on one mechanism from several host threads must
+ *    use distinct streams; workspace-using calls (chem_integrate, chem_integrate_adjoint)
+ *    serialise internally per mechanism.
+ *  - Functions return chem_err; no C++ exception crosses the ABI.  chem_last_error_message()
+ *    gives a human-readable detail of the last failure on the calling thread.
+ */
+#ifndef CHEM_H
+#define CHEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct chem_mech chem_mech;   /* loaded mechanism + compiled kernels; immutable after load */
+typedef struct chem_tape chem_tape;   /* adjoint tape: checkpoints and step records of one forward run */
+
+typedef enum {
+  CHEM_OK = 0,
+  CHEM_EINVAL = 1,       /* bad argument (null pointer, ld < n_cells, unknown option value ...) */
+  CHEM_ENOMEM = 2,       /* host or device allocation failed */
+  CHEM_EPARSE = 3,       /* mechanism file unreadable or malformed */
+  CHEM_EDEVICE = 4,      /* HIP runtime error (no device, launch failure ...) */
+  CHEM_ECOMPILE = 5,     /* generated kernel source failed to compile */
+  CHEM_ECELLS = 6,       /* only with CHEM_FLAG_CHECK_CELLS: at least one cell status != OK */
+  CHEM_EUNSUPPORTED = 7  /* valid request this build does not implement */
+} chem_err;
+
+/* per-cell status written by chem_integrate (int32 per cell) */
+enum {
+  CHEM_CELL_OK = 0,
+  CHEM_CELL_NEWTON_FAIL = 1,   /* backward Euler: Newton failed even after the deepest halving */
+  CHEM_CELL_DT_UNDERFLOW = 2,  /* Rosenbrock: step size fell below h_min after a rejection */
+  CHEM_CELL_MAX_STEPS = 3,     /* attempt budget exhausted */
+  CHEM_CELL_NONFINITE = 4,     /* non-finite input state */
+  CHEM_CELL_T_RANGE = 5        /* input temperature <= 0 */
+};
+
+enum { CHEM_BE = 0, CHEM_ROS2 = 1 };
+enum { CHEM_CONST_P = 0, CHEM_CONST_V = 1 };
+enum { CHEM_PERSISTENT = 0, CHEM_PLAIN = 1 };
+enum { CHEM_FLAG_CHECK_CELLS = 1 };  /* synchronise and return CHEM_ECELLS if a cell failed */
+
+/*
+ * Integrator options.  Fill with chem_default_options() and override fields.
+ *  method   CHEM_BE: n_steps fixed steps of dt/n_steps (n_steps 0 means 1), each solved by full Newton
+ *                    (G = I/h - J(y_k) re-evaluated every iteration, Section 3.2); a step whose
+ *                    Newton iteration fails is split in two halves recursively down to
+ *                    halving_max_depth (the step-halving of YASS, Appendix A.4).
+ *           CHEM_ROS2: two-stage Rosenbrock of Appendix A.3 from t = 0 to dt; adaptive step size
+ *                    (embedded first-order solution, weighted RMS error, rtol/atol on T [K] and
+ *                    on mass fractions) unless n_steps > 0, which gives fixed steps dt/n_steps.
+ *  energy   CHEM_CONST_P: omega_T = -sum H_i omega_i / sum C_i Cp_i (Appendix B)
+ *           CHEM_CONST_V: omega_T = -sum U_i omega_i / sum C_i Cv_i (Section 3)
+ *  form     CHEM_PERSISTENT: one persistent kernel, cells pulled from a work queue lane by lane.
+ *           CHEM_PLAIN: one kernel launch per substep (BE: per full step) over all cells.
+ *  Newton convergence: max_i |delta_i| / sc_i <= 1 with sc_T = newton_rtol T + newton_atol_T and,
+ *  for species, sc = (newton_atol_Y + newton_rtol |Y_i|) rho / W_i; divergence: the scaled
+ *  norm grows from the third iteration on.
+ */
+typedef struct {
+  int method;
+  int energy;
+  int form;
+  int flags;
+  double dt;
+  int n_steps;
+  int max_steps;
+  double rtol;
+  double atol;
+  double h_min;
+  int newton_max;
+  int halving_max_depth;
+  double newton_rtol;
+  double newton_atol_T;
+  double newton_atol_Y;
+} chem_integrator_opts;
+
+/* Defaults: BE, const-p, persistent, dt 1e-7, n_steps 0, max_steps 100000, rtol 1e-6, atol 1e-10,
+ * h_min 1e-20, newton_max 10, halving_max_depth 8, newton_rtol 1e-10, newton_atol_T 1e-8 K,
+ * newton_atol_Y 1e-14. */
+void chem_default_options(chem_integrator_opts* opts);
+
+/* Human-readable name of an error code (static string, never NULL). */
+const char* chem_error_string(chem_err err);
+/* Detail of the last error raised on the calling thread (static thread-local buffer). */
+const char* chem_last_error_message(void);
+
+/*
+ * Load a mechanism file (Cantera-like JSON: species with NASA-7 data; reactions of type
+ * elementary, three-body or falloff with Troe or Lindemann broadening; A, b, Ea in SI-kmol with
+ * Ea in J/kmol -- the units of the paper's worked example, Section 4.3), validate it, generate
+ * HIP source specialised to it (the code-generation step of Section 4.3) and compile it for the
+ * current device's architecture with hipRTC.  Compiled code objects are cached in cache_dir (or
+ * $CHEM_KERNEL_CACHE, else a per-user temp directory) keyed by a hash of the generated source
+ * and the compiler options.  The current HIP device at load time is the one the mechanism runs on.
+ * On success *out owns the mechanism; release it with chem_free_mechanism.
+ */
+chem_err chem_load_mechanism(const char* path, const char* cache_dir, chem_mech** out);
+void chem_free_mechanism(chem_mech* mech);
+
+/* Generate and compile the kernels of a mechanism file for gfx950 into cache_dir without needing
+ * a GPU (the ahead-of-time step of the build).  Writes the code-object path to path_out. */
+chem_err chem_precompile(const char* path, const char* cache_dir, char* path_out, size_t path_cap);
+
+/* Sizes: species, reactions, elements, state length n = ns + 1. */
+chem_err chem_mechanism_info(const chem_mech* mech, int* n_species, int* n_reactions, int* n_elements,
+                             int* n_state);
+/* HOST copies: molecular weights [ns] (kg/kmol) and the file's ln A [nr]. */
+chem_err chem_molecular_weights(const chem_mech* mech, double* W_host);
+chem_err chem_default_lnA(const chem_mech* mech, double* lnA_host);
+
+/*
+ * Species thermodynamics at temperatures T [ld] (Table 1, mass-specific): cp [J/kg/K], h [J/kg],
+ * s0 [J/kg/K] at p_ref, g0 = h - T s0 [J/kg]; each output [ns][ld].  Any output may be NULL.
+ */
+chem_err chem_thermo(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* T,
+                     double* cp, double* h, double* s, double* g, void* stream);
+
+/* Source term S(y) (eq. extracted_problem): dydt[n][ld] from y[n][ld]. */
+chem_err chem_source_terms(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* y,
+                           const double* lnA, int energy, double* dydt, void* stream);
+
+/* Analytic Jacobian dS/dy (eq. derivative_matrices_temp_evol): jac[n*n][ld], row-major i*n+j. */
+chem_err chem_jacobian(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* y,
+                       const double* lnA, int energy, double* jac, void* stream);
+
+/* Initial-state map: y = (T, C) with rho = p Wbar/(R T), C_i = rho Y_i / W_i.
+ * T[ld], p[ld], Y[ns][ld] in; y[n][ld] out. */
+chem_err chem_state_from_TPY(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* T,
+                             const double* p, const double* Y, double* y, void* stream);
+/* Mass fractions Y_i = W_i C_i / sum_k W_k C_k: Y[ns][ld] from y[n][ld]. */
+chem_err chem_mass_fractions(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* y,
+                             double* Y, void* stream);
+/* Pull-backs (vector-Jacobian products) of the two maps above, for gradients:
+ *  chem_state_from_TPY_vjp: given dL/dy [n][ld] at the map's output, writes dL/dT [ld] and
+ *                           dL/dY [ns][ld] (unconstrained partials; Y is not renormalised).
+ *  chem_mass_fractions_vjp: given dL/dY [ns][ld] and dL/dT_direct [ld] (nullable), writes
+ *                           dL/dy [n][ld] at y. */
+chem_err chem_state_from_TPY_vjp(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* T,
+                                 const double* p, const double* Y, const double* dL_dy, double* dL_dT,
+                                 double* dL_dY, void* stream);
+chem_err chem_mass_fractions_vjp(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* y,
+                                 const double* dL_dY, const double* dL_dT, double* dL_dy, void* stream);
+
+/*
+ * Integrate every cell over one split step: y[n][ld] is read and overwritten with the final
+ * state.  status [ld] (required) receives a CHEM_CELL_* code; counters (nullable) [3][ld]
+ * receives accepted substeps (BE: completed full steps), rejected attempts and Newton
+ * iterations.  A failed cell keeps its last accepted state.  tape (nullable, BE only) records
+ * what chem_integrate_adjoint needs; it must have been created for >= n_cells cells and the
+ * same options must be used.
+ */
+chem_err chem_integrate(const chem_mech* mech, int64_t n_cells, int64_t ld, double* y,
+                        const double* lnA, const chem_integrator_opts* opts, chem_tape* tape,
+                        int32_t* status, int32_t* counters, void* stream);
+
+/* Tape for the backward-Euler discrete adjoint: the state is checkpointed every
+ * checkpoint_every steps; the backward pass recomputes each segment from its checkpoint. */
+chem_err chem_tape_create(const chem_mech* mech, int64_t n_cells, int checkpoint_every, chem_tape** out);
+void chem_tape_free(chem_tape* tape);
+
+/*
+ * Discrete adjoint of the recorded backward-Euler integration.  Given dL/dy_N [n][ld] at the
+ * final state, writes dL/dy_0 [n][ld] and dL/dlnA [nr] (summed over cells, deterministic order).
+ * Every accepted (sub)step y -> y' with step h contributes
+ *   (I/h - J(y'))^T mu = lambda',  lambda = mu / h,  dL/dlnA_j += q_j(y') (sum_i nu_ij mu_i + mu_T dwT_j)
+ * where dwT_j is d omega_T / d lnA_j per unit q_j.  Uses the same lnA as the forward run.
+ */
+chem_err chem_integrate_adjoint(const chem_mech* mech, chem_tape* tape, const double* lnA,
+                                const double* dL_dyN, double* dL_dy0, double* dL_dlnA, void* stream);
+
+/*
+ * Kernel launch configuration of chem_integrate for a method/form: threads per block and blocks
+ * of the persistent grid (0 = library default).  chem_autotune times the candidates on the given
+ * cells (which it leaves unchanged) and keeps the fastest; chem_get_launch reports the current one.
+ */
+chem_err chem_set_launch(chem_mech* mech, int method, int form, int block, int grid);
+chem_err chem_get_launch(const chem_mech* mech, int method, int form, int* block, int* grid);
+chem_err chem_autotune(chem_mech* mech, int64_t n_cells, int64_t ld, const double* y, const double* lnA,
+                       const chem_integrator_opts* opts, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHEM_H */

@@ -184,6 +184,9 @@ def integrate_be(mech, y0, dt_total, n_steps, lnA=None, opt=None, record=False):
                 if record:
                     traj[c].append((yc.copy(), dt))
         for c in idx[~conv]:
+            if opt.halving_max_depth < 1:
+                status[c] = CELL_NEWTON_FAIL
+                continue
             # the whole step failed: split it into two halves, recursively
             rec = [] if record else None
             y1, ok, n1 = _be_substep_recursive(mech, y[c], 0.5 * dt, lnA, opt, 1, rec)

@@ -1,0 +1,234 @@
+"""ctypes binding of libchem.so with the same entry-point names as include/chem.h.
+
+Argument marshalling only: device arrays are torch tensors (float64 / int32, on the GPU) whose
+data pointers are passed through; the stream is torch's current HIP stream.  Every computation
+runs in the library's kernels.  If libchem.so is missing the import fails loudly -- there is no
+CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_PKG, "libchem.so")
+
+CHEM_OK = 0
+CHEM_BE, CHEM_ROS2 = 0, 1
+CHEM_CONST_P, CHEM_CONST_V = 0, 1
+CHEM_PERSISTENT, CHEM_PLAIN = 0, 1
+CHEM_FLAG_CHECK_CELLS = 1
+CELL_OK, CELL_NEWTON_FAIL, CELL_DT_UNDERFLOW, CELL_MAX_STEPS, CELL_NONFINITE, CELL_T_RANGE = range(6)
+
+# every symbol include/chem.h declares
+EXPORTED = [
+    "chem_default_options", "chem_error_string", "chem_last_error_message", "chem_load_mechanism",
+    "chem_free_mechanism", "chem_precompile", "chem_mechanism_info", "chem_molecular_weights",
+    "chem_default_lnA", "chem_thermo", "chem_source_terms", "chem_jacobian", "chem_state_from_TPY",
+    "chem_mass_fractions", "chem_state_from_TPY_vjp", "chem_mass_fractions_vjp", "chem_integrate",
+    "chem_tape_create", "chem_tape_free", "chem_integrate_adjoint", "chem_set_launch", "chem_get_launch",
+    "chem_autotune",
+]
+
+
+class ChemError(RuntimeError):
+    def __init__(self, code, where):
+        lib = load()
+        msg = lib.chem_error_string(code).decode()
+        detail = lib.chem_last_error_message().decode()
+        super().__init__(f"{where}: {msg} (code {code}){': ' + detail if detail else ''}")
+        self.code = code
+
+
+class IntegratorOptions(ctypes.Structure):
+    _fields_ = [
+        ("method", ctypes.c_int), ("energy", ctypes.c_int), ("form", ctypes.c_int), ("flags", ctypes.c_int),
+        ("dt", ctypes.c_double), ("n_steps", ctypes.c_int), ("max_steps", ctypes.c_int),
+        ("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("h_min", ctypes.c_double),
+        ("newton_max", ctypes.c_int), ("halving_max_depth", ctypes.c_int),
+        ("newton_rtol", ctypes.c_double), ("newton_atol_T", ctypes.c_double), ("newton_atol_Y", ctypes.c_double),
+    ]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I = ctypes.c_int
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def load():
+    """Load libchem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        raise ImportError(f"{_LIBPATH} is missing: build it with __graft_entry__.build() "
+                          "or python -m paper_2510_10005_amd.build")
+    # torch ships its own HIP runtime (same sonames as /opt/rocm).  Loading torch first makes
+    # libchem.so bind to that one copy, so torch's streams and allocations are valid handles in
+    # the library and only one HIP runtime lives in the process.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(_LIBPATH)
+    lib.chem_default_options.argtypes = [ctypes.POINTER(IntegratorOptions)]
+    lib.chem_default_options.restype = None
+    lib.chem_error_string.argtypes = [_I]
+    lib.chem_error_string.restype = ctypes.c_char_p
+    lib.chem_last_error_message.argtypes = []
+    lib.chem_last_error_message.restype = ctypes.c_char_p
+    lib.chem_load_mechanism.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(_P)]
+    lib.chem_free_mechanism.argtypes = [_P]
+    lib.chem_free_mechanism.restype = None
+    lib.chem_precompile.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t]
+    lib.chem_mechanism_info.argtypes = [_P] + [ctypes.POINTER(_I)] * 4
+    lib.chem_molecular_weights.argtypes = [_P, _D]
+    lib.chem_default_lnA.argtypes = [_P, _D]
+    lib.chem_thermo.argtypes = [_P, _I64, _I64, _P, _P, _P, _P, _P, _P]
+    lib.chem_source_terms.argtypes = [_P, _I64, _I64, _P, _P, _I, _P, _P]
+    lib.chem_jacobian.argtypes = [_P, _I64, _I64, _P, _P, _I, _P, _P]
+    lib.chem_state_from_TPY.argtypes = [_P, _I64, _I64, _P, _P, _P, _P, _P]
+    lib.chem_mass_fractions.argtypes = [_P, _I64, _I64, _P, _P, _P]
+    lib.chem_state_from_TPY_vjp.argtypes = [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P]
+    lib.chem_mass_fractions_vjp.argtypes = [_P, _I64, _I64, _P, _P, _P, _P, _P]
+    lib.chem_integrate.argtypes = [_P, _I64, _I64, _P, _P, ctypes.POINTER(IntegratorOptions), _P, _P, _P, _P]
+    lib.chem_tape_create.argtypes = [_P, _I64, _I, ctypes.POINTER(_P)]
+    lib.chem_tape_free.argtypes = [_P]
+    lib.chem_tape_free.restype = None
+    lib.chem_integrate_adjoint.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+    lib.chem_set_launch.argtypes = [_P, _I, _I, _I, _I]
+    lib.chem_get_launch.argtypes = [_P, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]
+    lib.chem_autotune.argtypes = [_P, _I64, _I64, _P, _P, ctypes.POINTER(IntegratorOptions), _P]
+    for name in EXPORTED:
+        f = getattr(lib, name)
+        if f.restype is ctypes.c_int or name not in ("chem_default_options", "chem_free_mechanism",
+                                                       "chem_tape_free", "chem_error_string",
+                                                       "chem_last_error_message"):
+            if name not in ("chem_error_string", "chem_last_error_message"):
+                f.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code, where):
+    if code != CHEM_OK:
+        raise ChemError(code, where)
+
+
+def default_options(**overrides) -> IntegratorOptions:
+    o = IntegratorOptions()
+    load().chem_default_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(f"unknown integrator option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def precompile(mech_path: str, cache_dir: str) -> str:
+    buf = ctypes.create_string_buffer(4096)
+    _check(load().chem_precompile(mech_path.encode(), cache_dir.encode(), buf, 4096), "chem_precompile")
+    return buf.value.decode()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Mechanism:
+    """A loaded mechanism: owns the library handle; all methods take/return torch tensors."""
+
+    def __init__(self, path: str, cache_dir: str | None = None):
+        self.lib = load()
+        h = _P()
+        _check(self.lib.chem_load_mechanism(path.encode(), cache_dir.encode() if cache_dir else None,
+                                            ctypes.byref(h)), f"chem_load_mechanism({path})")
+        self.handle = h
+        ns, nr, ne, n = _I(), _I(), _I(), _I()
+        _check(self.lib.chem_mechanism_info(h, ctypes.byref(ns), ctypes.byref(nr), ctypes.byref(ne),
+                                            ctypes.byref(n)), "chem_mechanism_info")
+        self.ns, self.nr, self.n_elements, self.n = ns.value, nr.value, ne.value, n.value
+        W = (ctypes.c_double * self.ns)()
+        _check(self.lib.chem_molecular_weights(h, W), "chem_molecular_weights")
+        self.W = list(W)
+        lnA = (ctypes.c_double * max(1, self.nr))()
+        _check(self.lib.chem_default_lnA(h, lnA), "chem_default_lnA")
+        self.lnA_default = list(lnA)[: self.nr]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.chem_free_mechanism(h)
+            self.handle = None
+
+    # each call mirrors the C entry point of the same name
+    def chem_thermo(self, n, ld, T, cp, h, s, g):
+        _check(self.lib.chem_thermo(self.handle, n, ld, _ptr(T), _ptr(cp), _ptr(h), _ptr(s), _ptr(g), _stream()),
+               "chem_thermo")
+
+    def chem_source_terms(self, n, ld, y, lnA, energy, dydt):
+        _check(self.lib.chem_source_terms(self.handle, n, ld, _ptr(y), _ptr(lnA), energy, _ptr(dydt), _stream()),
+               "chem_source_terms")
+
+    def chem_jacobian(self, n, ld, y, lnA, energy, jac):
+        _check(self.lib.chem_jacobian(self.handle, n, ld, _ptr(y), _ptr(lnA), energy, _ptr(jac), _stream()),
+               "chem_jacobian")
+
+    def chem_state_from_TPY(self, n, ld, T, p, Y, y):
+        _check(self.lib.chem_state_from_TPY(self.handle, n, ld, _ptr(T), _ptr(p), _ptr(Y), _ptr(y), _stream()),
+               "chem_state_from_TPY")
+
+    def chem_mass_fractions(self, n, ld, y, Y):
+        _check(self.lib.chem_mass_fractions(self.handle, n, ld, _ptr(y), _ptr(Y), _stream()), "chem_mass_fractions")
+
+    def chem_state_from_TPY_vjp(self, n, ld, T, p, Y, dLdy, dT, dY):
+        _check(self.lib.chem_state_from_TPY_vjp(self.handle, n, ld, _ptr(T), _ptr(p), _ptr(Y), _ptr(dLdy),
+                                                _ptr(dT), _ptr(dY), _stream()), "chem_state_from_TPY_vjp")
+
+    def chem_mass_fractions_vjp(self, n, ld, y, dY, dT, out):
+        _check(self.lib.chem_mass_fractions_vjp(self.handle, n, ld, _ptr(y), _ptr(dY), _ptr(dT), _ptr(out),
+                                                _stream()), "chem_mass_fractions_vjp")
+
+    def chem_integrate(self, n, ld, y, lnA, opts, tape, status, counters):
+        _check(self.lib.chem_integrate(self.handle, n, ld, _ptr(y), _ptr(lnA), ctypes.byref(opts),
+                                       tape.handle if tape is not None else None, _ptr(status), _ptr(counters),
+                                       _stream()), "chem_integrate")
+
+    def chem_integrate_adjoint(self, tape, lnA, dLdyN, dLdy0, dLdlnA):
+        _check(self.lib.chem_integrate_adjoint(self.handle, tape.handle, _ptr(lnA), _ptr(dLdyN), _ptr(dLdy0),
+                                               _ptr(dLdlnA), _stream()), "chem_integrate_adjoint")
+
+    def chem_set_launch(self, method, form, block, grid):
+        _check(self.lib.chem_set_launch(self.handle, method, form, block, grid), "chem_set_launch")
+
+    def chem_get_launch(self, method, form):
+        b, g = _I(), _I()
+        _check(self.lib.chem_get_launch(self.handle, method, form, ctypes.byref(b), ctypes.byref(g)),
+               "chem_get_launch")
+        return b.value, g.value
+
+    def chem_autotune(self, n, ld, y, lnA, opts):
+        _check(self.lib.chem_autotune(self.handle, n, ld, _ptr(y), _ptr(lnA), ctypes.byref(opts), _stream()),
+               "chem_autotune")
+
+
+class Tape:
+    def __init__(self, mech: Mechanism, n_cells: int, checkpoint_every: int):
+        self.lib = mech.lib
+        h = _P()
+        _check(self.lib.chem_tape_create(mech.handle, n_cells, checkpoint_every, ctypes.byref(h)), "chem_tape_create")
+        self.handle = h
+        self.mech = mech   # keeps the mechanism alive while the tape exists
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.chem_tape_free(h)
+            self.handle = None

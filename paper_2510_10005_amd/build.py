@@ -1,0 +1,54 @@
+"""Build libchem.so (host C++ with the HIP runtime and hipRTC) in-tree, and precompile kernels.
+
+libchem.so holds the mechanism parser, the HIP code generator, the hipRTC driver and the C ABI
+of include/chem.h.  The device code is generated per mechanism and compiled for gfx950 by hipRTC;
+``precompile`` does that ahead of time for given mechanism files into a kernel cache directory so
+that a run on the GPU finds the code objects already built.
+"""
+
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB = os.path.join(PKG, "libchem.so")
+INCLUDE = os.path.join(ROOT, "include")
+KERNEL_CACHE = os.path.join(ROOT, "_build", "kernels")
+SOURCES = ["chem.cpp", "codegen.cpp", "mechanism.cpp"]
+
+
+def build_library(verbose: bool = True) -> str:
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    cmd = [hipcc, "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
+           "-I", INCLUDE, "-I", CSRC, "-o", LIB + ".tmp"]
+    cmd += [os.path.join(CSRC, s) for s in SOURCES]
+    cmd += ["-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+def precompile(mech_paths, cache_dir: str = KERNEL_CACHE, verbose: bool = True):
+    """Generate and hipRTC-compile (gfx950) the kernels of each mechanism file into cache_dir."""
+    from . import _binding
+    out = []
+    for p in mech_paths:
+        path = _binding.precompile(p, cache_dir)
+        if verbose:
+            print(f"precompiled {os.path.basename(p)} -> {path}", flush=True)
+        out.append(path)
+    return out
+
+
+if __name__ == "__main__":
+    build_library()
+    if len(sys.argv) > 1:
+        sys.path.insert(0, ROOT)
+        from paper_2510_10005_amd import build as b  # noqa: E402
+        b.precompile(sys.argv[1:])

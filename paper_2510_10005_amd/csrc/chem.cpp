@@ -1,0 +1,683 @@
+// libchem.so: C ABI (include/chem.h) over per-mechanism generated HIP kernels for gfx950.
+#include "chem.h"
+
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "mechanism.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+chem_err fail(chem_err e, const std::string& msg) {
+  g_last_error = msg;
+  return e;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return fail(CHEM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));         \
+  } while (0)
+
+// Registers per lane beyond which the per-cell matrix lives in a device-memory workspace.
+constexpr int kDenseLimit = 24;
+constexpr int kMaxBlock = 256;
+
+const char* kKernelNames[] = {
+    "chem_k_thermo",        "chem_k_source",           "chem_k_jacobian",         "chem_k_state_from_TPY",
+    "chem_k_mass_fractions", "chem_k_state_from_TPY_vjp", "chem_k_mass_fractions_vjp", "chem_k_fill_u64",
+    "chem_k_ros2_persistent", "chem_k_ros2_init",       "chem_k_ros2_step",        "chem_k_be_persistent",
+    "chem_k_be_init",       "chem_k_be_step",          "chem_k_be_adjoint",       "chem_k_reduce_blocks"};
+enum KernelId {
+  K_THERMO, K_SOURCE, K_JACOBIAN, K_TPY, K_MASSFRAC, K_TPY_VJP, K_MASSFRAC_VJP, K_FILL_U64,
+  K_ROS2_PERSISTENT, K_ROS2_INIT, K_ROS2_STEP, K_BE_PERSISTENT, K_BE_INIT, K_BE_STEP, K_BE_ADJOINT,
+  K_REDUCE_BLOCKS, K_COUNT
+};
+
+struct DevChemOpts {  // layout mirrors ChemOpts in the generated source
+  double dt, rtol, atol, h_min;
+  double newton_rtol, newton_atol_T, newton_atol_Y;
+  int n_steps, max_steps, newton_max, halving_max_depth, energy, ckpt_every;
+};
+
+uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull) {
+  for (unsigned char c : s) {
+    h ^= c;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+std::string default_cache_dir() {
+  const char* env = std::getenv("CHEM_KERNEL_CACHE");
+  if (env && *env) return env;
+  return "/tmp/chem_kernel_cache_" + std::to_string(static_cast<long>(getuid()));
+}
+
+void mkdirs(const std::string& path) {
+  std::string cur;
+  for (size_t i = 0; i < path.size(); ++i) {
+    cur += path[i];
+    if (path[i] == '/' || i + 1 == path.size()) mkdir(cur.c_str(), 0755);
+  }
+}
+
+bool read_file(const std::string& p, std::string& out) {
+  std::ifstream f(p, std::ios::binary);
+  if (!f) return false;
+  std::ostringstream ss;
+  ss << f.rdbuf();
+  out = ss.str();
+  return true;
+}
+
+std::vector<std::string> compile_options(const std::string& arch) {
+  return {"--offload-arch=" + arch, "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+}
+
+// generate + compile (or fetch from the cache); returns the code object bytes
+chem_err build_code_object(const chem::Mechanism& m, const std::string& arch, const std::string& cache_dir,
+                           std::string& code, std::string& cache_path) {
+  const std::string src = chem::generate_source(m, kDenseLimit);
+  auto opts = compile_options(arch);
+  int rtc_major = 0, rtc_minor = 0;
+  hiprtcVersion(&rtc_major, &rtc_minor);
+  std::string key = src + "|" + std::to_string(rtc_major) + "." + std::to_string(rtc_minor);
+  for (auto& o : opts) key += "|" + o;
+  char name[64];
+  std::snprintf(name, sizeof(name), "chem_%016llx.hsaco", static_cast<unsigned long long>(fnv1a(key)));
+  cache_path = cache_dir + "/" + name;
+  if (read_file(cache_path, code) && !code.empty()) return CHEM_OK;
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), "chem_mechanism.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+    return fail(CHEM_ECOMPILE, "hiprtcCreateProgram failed");
+  std::vector<const char*> copts;
+  for (auto& o : opts) copts.push_back(o.c_str());
+  hiprtcResult rc = hiprtcCompileProgram(prog, static_cast<int>(copts.size()), copts.data());
+  if (rc != HIPRTC_SUCCESS) {
+    size_t ls = 0;
+    hiprtcGetProgramLogSize(prog, &ls);
+    std::string log(ls, '\0');
+    if (ls) hiprtcGetProgramLog(prog, &log[0]);
+    hiprtcDestroyProgram(&prog);
+    if (log.size() > 4000) log = log.substr(0, 4000) + "...";
+    return fail(CHEM_ECOMPILE, "hipRTC compile failed: " + log);
+  }
+  size_t cs = 0;
+  hiprtcGetCodeSize(prog, &cs);
+  code.assign(cs, '\0');
+  hiprtcGetCode(prog, &code[0]);
+  hiprtcDestroyProgram(&prog);
+  mkdirs(cache_dir);
+  const std::string tmp = cache_path + ".tmp" + std::to_string(static_cast<long>(getpid()));
+  {
+    std::ofstream f(tmp, std::ios::binary);
+    f.write(code.data(), static_cast<std::streamsize>(code.size()));
+  }
+  std::rename(tmp.c_str(), cache_path.c_str());
+  return CHEM_OK;
+}
+
+chem_err parse_file(const char* path, chem::Mechanism& m) {
+  if (!path) return fail(CHEM_EINVAL, "null mechanism path");
+  std::string text;
+  if (!read_file(path, text)) return fail(CHEM_EPARSE, std::string("cannot read ") + path);
+  try {
+    m = chem::parse_mechanism(text);
+  } catch (const std::exception& e) {
+    return fail(CHEM_EPARSE, std::string(path) + ": " + e.what());
+  }
+  return CHEM_OK;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  chem_err ensure(size_t b) {
+    if (b <= bytes) return CHEM_OK;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (hipMalloc(&p, b) != hipSuccess) return fail(CHEM_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+    bytes = b;
+    return CHEM_OK;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace
+
+struct chem_tape {
+  const chem_mech* mech = nullptr;
+  int64_t n_cells = 0;
+  int64_t ld = 0;
+  int ckpt_every = 1;
+  bool recorded = false;
+  DevChemOpts opts{};
+  DevBuf ckpt, nsub, status;
+  int ckpt_slots = 0, nsub_steps = 0;
+};
+
+struct chem_mech {
+  chem::Mechanism m;
+  int device = 0;
+  int num_cu = 0;
+  std::string arch;
+  hipModule_t module = nullptr;
+  hipFunction_t fn[K_COUNT] = {};
+  bool dense = true;
+  DevBuf lnA_default, queue, ws, wst, counters_internal, running, seg, gws, gpart;
+  unsigned int* running_host = nullptr;
+  int launch_block[2][2] = {{0, 0}, {0, 0}};  // [method][form]
+  int launch_grid[2][2] = {{0, 0}, {0, 0}};
+  std::mutex mu;
+  ~chem_mech() {
+    if (running_host) (void)hipHostFree(running_host);
+    if (module) (void)hipModuleUnload(module);
+  }
+};
+
+namespace {
+
+chem_err launch(const chem_mech* M, KernelId k, unsigned grid, unsigned block, hipStream_t s, void** args,
+                unsigned shmem = 0) {
+  if (grid == 0) return CHEM_OK;
+  hipError_t e = hipModuleLaunchKernel(M->fn[k], grid, 1, 1, block, 1, 1, shmem, s, args, nullptr);
+  if (e != hipSuccess) return fail(CHEM_EDEVICE, std::string("launch of ") + kKernelNames[k] + ": " + hipGetErrorString(e));
+  return CHEM_OK;
+}
+
+unsigned blocks_for(int64_t n, int block) { return static_cast<unsigned>((n + block - 1) / block); }
+
+chem_err check_cells(int64_t n_cells, int64_t ld) {
+  if (n_cells < 0) return fail(CHEM_EINVAL, "n_cells must be >= 0");
+  if (ld < n_cells) return fail(CHEM_EINVAL, "ld must be >= n_cells");
+  if (n_cells > (int64_t(1) << 40)) return fail(CHEM_EINVAL, "n_cells too large");
+  return CHEM_OK;
+}
+
+DevChemOpts to_dev(const chem_integrator_opts& o, int ckpt_every) {
+  DevChemOpts d{};
+  d.dt = o.dt;
+  d.rtol = o.rtol;
+  d.atol = o.atol;
+  d.h_min = o.h_min;
+  d.newton_rtol = o.newton_rtol;
+  d.newton_atol_T = o.newton_atol_T;
+  d.newton_atol_Y = o.newton_atol_Y;
+  d.n_steps = (o.method == CHEM_BE && o.n_steps < 1) ? 1 : o.n_steps;
+  d.max_steps = o.max_steps;
+  d.newton_max = o.newton_max;
+  d.halving_max_depth = o.halving_max_depth;
+  d.energy = o.energy;
+  d.ckpt_every = ckpt_every > 0 ? ckpt_every : 1;
+  return d;
+}
+
+chem_err validate_opts(const chem_integrator_opts* o) {
+  if (!o) return fail(CHEM_EINVAL, "null options");
+  if (o->method != CHEM_BE && o->method != CHEM_ROS2) return fail(CHEM_EINVAL, "unknown method");
+  if (o->energy != CHEM_CONST_P && o->energy != CHEM_CONST_V) return fail(CHEM_EINVAL, "unknown energy mode");
+  if (o->form != CHEM_PERSISTENT && o->form != CHEM_PLAIN) return fail(CHEM_EINVAL, "unknown form");
+  if (!(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(CHEM_EINVAL, "dt must be positive and finite");
+  if (o->n_steps < 0) return fail(CHEM_EINVAL, "n_steps must be >= 0");
+  if (o->max_steps < 1) return fail(CHEM_EINVAL, "max_steps must be >= 1");
+  if (o->method == CHEM_ROS2 && (!(o->rtol > 0.0) || !(o->atol > 0.0))) return fail(CHEM_EINVAL, "rtol and atol must be positive");
+  if (!(o->h_min >= 0.0)) return fail(CHEM_EINVAL, "h_min must be >= 0");
+  if (o->newton_max < 1 || o->halving_max_depth < 0 || o->halving_max_depth > 30)
+    return fail(CHEM_EINVAL, "newton_max >= 1 and 0 <= halving_max_depth <= 30 required");
+  return CHEM_OK;
+}
+
+// blocks per CU the runtime reports for a kernel at this block size (>= 1)
+int occupancy_blocks(const chem_mech* M, KernelId k, int block) {
+  int nb = 0;
+  if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, M->fn[k], block, 0) != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+void persistent_config(const chem_mech* M, int method, KernelId k, int& block, unsigned& grid) {
+  block = M->launch_block[method][CHEM_PERSISTENT] ? M->launch_block[method][CHEM_PERSISTENT] : 64;
+  grid = M->launch_grid[method][CHEM_PERSISTENT]
+             ? static_cast<unsigned>(M->launch_grid[method][CHEM_PERSISTENT])
+             : static_cast<unsigned>(occupancy_blocks(M, k, block) * M->num_cu);
+}
+
+}  // namespace
+
+// ============================================================================ ABI
+extern "C" {
+
+void chem_default_options(chem_integrator_opts* o) {
+  if (!o) return;
+  o->method = CHEM_BE;
+  o->energy = CHEM_CONST_P;
+  o->form = CHEM_PERSISTENT;
+  o->flags = 0;
+  o->dt = 1e-7;
+  o->n_steps = 0;
+  o->max_steps = 100000;
+  o->rtol = 1e-6;
+  o->atol = 1e-10;
+  o->h_min = 1e-20;
+  o->newton_max = 10;
+  o->halving_max_depth = 8;
+  o->newton_rtol = 1e-10;
+  o->newton_atol_T = 1e-8;
+  o->newton_atol_Y = 1e-14;
+}
+
+const char* chem_error_string(chem_err e) {
+  switch (e) {
+    case CHEM_OK: return "ok";
+    case CHEM_EINVAL: return "invalid argument";
+    case CHEM_ENOMEM: return "out of memory";
+    case CHEM_EPARSE: return "mechanism parse error";
+    case CHEM_EDEVICE: return "HIP device error";
+    case CHEM_ECOMPILE: return "kernel compilation failed";
+    case CHEM_ECELLS: return "one or more cells failed";
+    case CHEM_EUNSUPPORTED: return "unsupported request";
+  }
+  return "unknown error";
+}
+
+const char* chem_last_error_message(void) { return g_last_error.c_str(); }
+
+chem_err chem_precompile(const char* path, const char* cache_dir, char* path_out, size_t cap) {
+  chem::Mechanism m;
+  chem_err e = parse_file(path, m);
+  if (e) return e;
+  std::string code, cpath;
+  e = build_code_object(m, "gfx950", cache_dir ? cache_dir : default_cache_dir(), code, cpath);
+  if (e) return e;
+  if (path_out && cap) {
+    std::strncpy(path_out, cpath.c_str(), cap - 1);
+    path_out[cap - 1] = '\0';
+  }
+  return CHEM_OK;
+}
+
+chem_err chem_load_mechanism(const char* path, const char* cache_dir, chem_mech** out) {
+  if (!out) return fail(CHEM_EINVAL, "null output pointer");
+  *out = nullptr;
+  std::unique_ptr<chem_mech> M(new chem_mech());
+  chem_err e = parse_file(path, M->m);
+  if (e) return e;
+  HIP_TRY(hipGetDevice(&M->device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, M->device));
+  M->num_cu = prop.multiProcessorCount;
+  std::string arch = prop.gcnArchName;
+  M->arch = arch.substr(0, arch.find(':'));
+  std::string code, cpath;
+  e = build_code_object(M->m, M->arch, cache_dir ? cache_dir : default_cache_dir(), code, cpath);
+  if (e) return e;
+  HIP_TRY(hipModuleLoadData(&M->module, code.data()));
+  for (int k = 0; k < K_COUNT; ++k) HIP_TRY(hipModuleGetFunction(&M->fn[k], M->module, kKernelNames[k]));
+  M->dense = M->m.n() <= kDenseLimit;
+  std::vector<double> lnA(std::max(1, M->m.nr()), 0.0);
+  for (int j = 0; j < M->m.nr(); ++j) lnA[j] = M->m.reactions[j].k.lnA;
+  if ((e = M->lnA_default.ensure(lnA.size() * sizeof(double)))) return e;
+  HIP_TRY(hipMemcpy(M->lnA_default.p, lnA.data(), lnA.size() * sizeof(double), hipMemcpyHostToDevice));
+  if ((e = M->queue.ensure(sizeof(uint64_t)))) return e;
+  if ((e = M->running.ensure(64 * sizeof(unsigned int)))) return e;
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&M->running_host), sizeof(unsigned int), hipHostMallocDefault));
+  *out = M.release();
+  return CHEM_OK;
+}
+
+void chem_free_mechanism(chem_mech* mech) { delete mech; }
+
+chem_err chem_mechanism_info(const chem_mech* M, int* ns, int* nr, int* ne, int* n) {
+  if (!M) return fail(CHEM_EINVAL, "null mechanism");
+  if (ns) *ns = M->m.ns();
+  if (nr) *nr = M->m.nr();
+  if (ne) *ne = static_cast<int>(M->m.elements.size());
+  if (n) *n = M->m.n();
+  return CHEM_OK;
+}
+
+chem_err chem_molecular_weights(const chem_mech* M, double* W) {
+  if (!M || !W) return fail(CHEM_EINVAL, "null argument");
+  for (int i = 0; i < M->m.ns(); ++i) W[i] = M->m.species[i].W;
+  return CHEM_OK;
+}
+
+chem_err chem_default_lnA(const chem_mech* M, double* lnA) {
+  if (!M || !lnA) return fail(CHEM_EINVAL, "null argument");
+  for (int j = 0; j < M->m.nr(); ++j) lnA[j] = M->m.reactions[j].k.lnA;
+  return CHEM_OK;
+}
+
+chem_err chem_thermo(const chem_mech* M, int64_t n, int64_t ld, const double* T, double* cp, double* h, double* s,
+                     double* g, void* stream) {
+  if (!M || !T) return fail(CHEM_EINVAL, "null argument");
+  if (chem_err e = check_cells(n, ld)) return e;
+  void* args[] = {&n, &ld, &T, &cp, &h, &s, &g};
+  return launch(M, K_THERMO, blocks_for(n, 256), 256, static_cast<hipStream_t>(stream), args);
+}
+
+chem_err chem_source_terms(const chem_mech* M, int64_t n, int64_t ld, const double* y, const double* lnA, int energy,
+                           double* dydt, void* stream) {
+  if (!M || !y || !dydt) return fail(CHEM_EINVAL, "null argument");
+  if (chem_err e = check_cells(n, ld)) return e;
+  if (energy != CHEM_CONST_P && energy != CHEM_CONST_V) return fail(CHEM_EINVAL, "unknown energy mode");
+  const double* la = lnA ? lnA : M->lnA_default.as<double>();
+  void* args[] = {&n, &ld, &y, &la, &energy, &dydt};
+  return launch(M, K_SOURCE, blocks_for(n, 256), 256, static_cast<hipStream_t>(stream), args);
+}
+
+chem_err chem_jacobian(const chem_mech* M, int64_t n, int64_t ld, const double* y, const double* lnA, int energy,
+                       double* jac, void* stream) {
+  if (!M || !y || !jac) return fail(CHEM_EINVAL, "null argument");
+  if (chem_err e = check_cells(n, ld)) return e;
+  if (energy != CHEM_CONST_P && energy != CHEM_CONST_V) return fail(CHEM_EINVAL, "unknown energy mode");
+  const double* la = lnA ? lnA : M->lnA_default.as<double>();
+  void* args[] = {&n, &ld, &y, &la, &energy, &jac};
+  return launch(M, K_JACOBIAN, blocks_for(n, 256), 256, static_cast<hipStream_t>(stream), args);
+}
+
+chem_err chem_state_from_TPY(const chem_mech* M, int64_t n, int64_t ld, const double* T, const double* p,
+                             const double* Y, double* y, void* stream) {
+  if (!M || !T || !p || !Y || !y) return fail(CHEM_EINVAL, "null argument");
+  if (chem_err e = check_cells(n, ld)) return e;
+  void* args[] = {&n, &ld, &T, &p, &Y, &y};
+  return launch(M, K_TPY, blocks_for(n, 256), 256, static_cast<hipStream_t>(stream), args);
+}
+
+chem_err chem_mass_fractions(const chem_mech* M, int64_t n, int64_t ld, const double* y, double* Y, void* stream) {
+  if (!M || !y || !Y) return fail(CHEM_EINVAL, "null argument");
+  if (chem_err e = check_cells(n, ld)) return e;
+  void* args[] = {&n, &ld, &y, &Y};
+  return launch(M, K_MASSFRAC, blocks_for(n, 256), 256, static_cast<hipStream_t>(stream), args);
+}
+
+chem_err chem_state_from_TPY_vjp(const chem_mech* M, int64_t n, int64_t ld, const double* T, const double* p,
+                                 const double* Y, const double* dLdy, double* dT, double* dY, void* stream) {
+  if (!M || !T || !p || !Y || !dLdy || !dT || !dY) return fail(CHEM_EINVAL, "null argument");
+  if (chem_err e = check_cells(n, ld)) return e;
+  void* args[] = {&n, &ld, &T, &p, &Y, &dLdy, &dT, &dY};
+  return launch(M, K_TPY_VJP, blocks_for(n, 256), 256, static_cast<hipStream_t>(stream), args);
+}
+
+chem_err chem_mass_fractions_vjp(const chem_mech* M, int64_t n, int64_t ld, const double* y, const double* dY,
+                                 const double* dT, double* out, void* stream) {
+  if (!M || !y || !dY || !out) return fail(CHEM_EINVAL, "null argument");
+  if (chem_err e = check_cells(n, ld)) return e;
+  void* args[] = {&n, &ld, &y, &dY, &dT, &out};
+  return launch(M, K_MASSFRAC_VJP, blocks_for(n, 256), 256, static_cast<hipStream_t>(stream), args);
+}
+
+chem_err chem_tape_create(const chem_mech* M, int64_t n_cells, int ckpt_every, chem_tape** out) {
+  if (!M || !out) return fail(CHEM_EINVAL, "null argument");
+  if (n_cells < 0 || ckpt_every < 1) return fail(CHEM_EINVAL, "n_cells >= 0 and checkpoint_every >= 1 required");
+  chem_tape* t = new chem_tape();
+  t->mech = M;
+  t->n_cells = n_cells;
+  t->ckpt_every = ckpt_every;
+  *out = t;
+  return CHEM_OK;
+}
+
+void chem_tape_free(chem_tape* t) { delete t; }
+
+static chem_err fill_u64(chem_mech* M, uint64_t* p, int n, uint64_t v, hipStream_t s) {
+  void* args[] = {&p, &n, &v};
+  return launch(M, K_FILL_U64, blocks_for(n, 64), 64, s, args);
+}
+
+chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, const double* lnA,
+                        const chem_integrator_opts* opts, chem_tape* tape, int32_t* status, int32_t* counters,
+                        void* stream) {
+  chem_mech* M = const_cast<chem_mech*>(Mc);
+  if (!M || !y || !status) return fail(CHEM_EINVAL, "null argument");
+  if (chem_err e = check_cells(n, ld)) return e;
+  if (chem_err e = validate_opts(opts)) return e;
+  if (tape) {
+    if (opts->method != CHEM_BE) return fail(CHEM_EUNSUPPORTED, "the adjoint tape is implemented for backward Euler");
+    if (tape->mech != M) return fail(CHEM_EINVAL, "tape belongs to another mechanism");
+    if (tape->n_cells < n) return fail(CHEM_EINVAL, "tape was created for fewer cells");
+  }
+  if (n == 0) return CHEM_OK;
+  std::lock_guard<std::mutex> lock(M->mu);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const double* la = lnA ? lnA : M->lnA_default.as<double>();
+  const int NY = M->m.n();
+  DevChemOpts o = to_dev(*opts, tape ? tape->ckpt_every : 1);
+  chem_err e;
+  int* cnt = counters;
+  if (!cnt) {
+    if ((e = M->counters_internal.ensure(sizeof(int) * 3 * static_cast<size_t>(ld)))) return e;
+    cnt = M->counters_internal.as<int>();
+  }
+  double* ckpt = nullptr;
+  unsigned short* nsub = nullptr;
+  if (tape) {
+    const int slots = o.n_steps / o.ckpt_every + 1;
+    if ((e = tape->ckpt.ensure(sizeof(double) * static_cast<size_t>(slots) * NY * ld))) return e;
+    if ((e = tape->nsub.ensure(sizeof(unsigned short) * static_cast<size_t>(o.n_steps) * ld))) return e;
+    if ((e = tape->status.ensure(sizeof(int) * static_cast<size_t>(ld)))) return e;
+    ckpt = tape->ckpt.as<double>();
+    nsub = tape->nsub.as<unsigned short>();
+    tape->ld = ld;
+    tape->n_cells = n;
+    tape->opts = o;
+    tape->recorded = false;
+  }
+  const int method = opts->method;
+  if (opts->form == CHEM_PERSISTENT) {
+    const KernelId k = method == CHEM_ROS2 ? K_ROS2_PERSISTENT : K_BE_PERSISTENT;
+    int block;
+    unsigned grid;
+    persistent_config(M, method, k, block, grid);
+    int64_t slots = static_cast<int64_t>(grid) * block;
+    double* ws = nullptr;
+    if (!M->dense) {
+      if ((e = M->ws.ensure(sizeof(double) * static_cast<size_t>(NY) * NY * slots))) return e;
+      ws = M->ws.as<double>();
+    }
+    uint64_t* q = M->queue.as<uint64_t>();
+    if ((e = fill_u64(M, q, 1, 0, s))) return e;
+    if (method == CHEM_ROS2) {
+      void* args[] = {&n, &ld, &y, &la, &o, &status, &cnt, &q, &ws, &slots};
+      if ((e = launch(M, k, grid, block, s, args))) return e;
+    } else {
+      void* args[] = {&n, &ld, &y, &la, &o, &status, &cnt, &q, &ws, &slots, &ckpt, &nsub};
+      if ((e = launch(M, k, grid, block, s, args))) return e;
+    }
+  } else {
+    const int block = M->launch_block[method][CHEM_PLAIN] ? M->launch_block[method][CHEM_PLAIN] : 64;
+    const unsigned grid = blocks_for(n, block);
+    int64_t slots = n;
+    double* ws = nullptr;
+    if (!M->dense) {
+      if ((e = M->ws.ensure(sizeof(double) * static_cast<size_t>(NY) * NY * slots))) return e;
+      ws = M->ws.as<double>();
+    }
+    if (method == CHEM_ROS2) {
+      if ((e = M->wst.ensure(sizeof(double) * 4 * static_cast<size_t>(n)))) return e;
+      double* wst = M->wst.as<double>();
+      {
+        void* args[] = {&n, &ld, &y, &status, &cnt, &wst};
+        if ((e = launch(M, K_ROS2_INIT, blocks_for(n, 256), 256, s, args))) return e;
+      }
+      unsigned int* run = M->running.as<unsigned int>();
+      const int batch = 16;
+      int64_t launched = 0;
+      while (launched <= opts->max_steps) {
+        if ((e = fill_u64(M, reinterpret_cast<uint64_t*>(run), 32, 0, s))) return e;
+        for (int b = 0; b < batch; ++b) {
+          unsigned int* slot = run + b;
+          void* args[] = {&n, &ld, &y, &la, &o, &status, &cnt, &wst, &slot, &ws, &slots};
+          if ((e = launch(M, K_ROS2_STEP, grid, block, s, args))) return e;
+        }
+        launched += batch;
+        HIP_TRY(hipMemcpyAsync(M->running_host, run + batch - 1, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (*M->running_host == 0) break;
+      }
+    } else {
+      {
+        void* args[] = {&n, &ld, &y, &status, &cnt, &ckpt};
+        if ((e = launch(M, K_BE_INIT, blocks_for(n, 256), 256, s, args))) return e;
+      }
+      for (int st = 0; st < o.n_steps; ++st) {
+        void* args[] = {&n, &ld, &y, &la, &o, &status, &cnt, &ws, &slots, &ckpt, &nsub};
+        if ((e = launch(M, K_BE_STEP, grid, block, s, args))) return e;
+      }
+    }
+  }
+  if (tape) {
+    HIP_TRY(hipMemcpyAsync(tape->status.p, status, sizeof(int) * static_cast<size_t>(n), hipMemcpyDeviceToDevice, s));
+    tape->recorded = true;
+  }
+  if (opts->flags & CHEM_FLAG_CHECK_CELLS) {
+    std::vector<int> h(static_cast<size_t>(n));
+    HIP_TRY(hipMemcpyAsync(h.data(), status, sizeof(int) * h.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int v : h)
+      if (v != CHEM_CELL_OK) return fail(CHEM_ECELLS, "at least one cell did not finish with status OK");
+  }
+  return CHEM_OK;
+}
+
+chem_err chem_integrate_adjoint(const chem_mech* Mc, chem_tape* tape, const double* lnA, const double* dLdyN,
+                                double* dLdy0, double* dLdlnA, void* stream) {
+  chem_mech* M = const_cast<chem_mech*>(Mc);
+  if (!M || !tape || !dLdyN || !dLdy0 || !dLdlnA) return fail(CHEM_EINVAL, "null argument");
+  if (tape->mech != M) return fail(CHEM_EINVAL, "tape belongs to another mechanism");
+  if (!tape->recorded) return fail(CHEM_EINVAL, "tape holds no recorded forward run");
+  std::lock_guard<std::mutex> lock(M->mu);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int64_t n = tape->n_cells, ld = tape->ld;
+  const double* la = lnA ? lnA : M->lnA_default.as<double>();
+  const int NY = M->m.n(), NR = std::max(1, M->m.nr());
+  const int block = 256;
+  const unsigned grid = std::max(1u, std::min(blocks_for(n, block), static_cast<unsigned>(
+                                                                    occupancy_blocks(M, K_BE_ADJOINT, block) * M->num_cu)));
+  int64_t total = static_cast<int64_t>(grid) * block;
+  chem_err e;
+  const int K = tape->opts.ckpt_every;
+  if ((e = M->seg.ensure(sizeof(double) * static_cast<size_t>(K) * NY * total))) return e;
+  if ((e = M->gpart.ensure(sizeof(double) * static_cast<size_t>(grid) * NR))) return e;
+  double* ws = nullptr;
+  double* gws = nullptr;
+  if (!M->dense) {
+    if ((e = M->ws.ensure(sizeof(double) * static_cast<size_t>(NY) * NY * total))) return e;
+    if ((e = M->gws.ensure(sizeof(double) * static_cast<size_t>(NR) * total))) return e;
+    ws = M->ws.as<double>();
+    gws = M->gws.as<double>();
+  }
+  DevChemOpts o = tape->opts;
+  const int* st = tape->status.as<int>();
+  const double* ck = tape->ckpt.as<double>();
+  const unsigned short* ns = tape->nsub.as<unsigned short>();
+  double* seg = M->seg.as<double>();
+  double* gp = M->gpart.as<double>();
+  {
+    void* args[] = {&n, &ld, &la, &o, &st, &ck, &ns, &dLdyN, &dLdy0, &gp, &seg, &total, &ws, &total, &gws};
+    if ((e = launch(M, K_BE_ADJOINT, grid, block, s, args))) return e;
+  }
+  int nb = static_cast<int>(grid);
+  void* args[] = {&nb, &gp, &dLdlnA};
+  return launch(M, K_REDUCE_BLOCKS, blocks_for(NR, 64), 64, s, args);
+}
+
+chem_err chem_set_launch(chem_mech* M, int method, int form, int block, int grid) {
+  if (!M) return fail(CHEM_EINVAL, "null mechanism");
+  if ((method != CHEM_BE && method != CHEM_ROS2) || (form != CHEM_PERSISTENT && form != CHEM_PLAIN))
+    return fail(CHEM_EINVAL, "unknown method or form");
+  if (block != 0 && (block < 64 || block > kMaxBlock || block % 64)) return fail(CHEM_EINVAL, "block must be 64..256, a multiple of 64");
+  if (grid < 0) return fail(CHEM_EINVAL, "grid must be >= 0");
+  M->launch_block[method][form] = block;
+  M->launch_grid[method][form] = grid;
+  return CHEM_OK;
+}
+
+chem_err chem_get_launch(const chem_mech* M, int method, int form, int* block, int* grid) {
+  if (!M || !block || !grid) return fail(CHEM_EINVAL, "null argument");
+  if ((method != CHEM_BE && method != CHEM_ROS2) || (form != CHEM_PERSISTENT && form != CHEM_PLAIN))
+    return fail(CHEM_EINVAL, "unknown method or form");
+  if (form == CHEM_PERSISTENT) {
+    int b;
+    unsigned g;
+    persistent_config(M, method, method == CHEM_ROS2 ? K_ROS2_PERSISTENT : K_BE_PERSISTENT, b, g);
+    *block = b;
+    *grid = static_cast<int>(g);
+  } else {
+    *block = M->launch_block[method][form] ? M->launch_block[method][form] : 64;
+    *grid = 0;
+  }
+  return CHEM_OK;
+}
+
+chem_err chem_autotune(chem_mech* M, int64_t n, int64_t ld, const double* y, const double* lnA,
+                       const chem_integrator_opts* opts, void* stream) {
+  if (!M || !y) return fail(CHEM_EINVAL, "null argument");
+  if (chem_err e = check_cells(n, ld)) return e;
+  if (chem_err e = validate_opts(opts)) return e;
+  if (opts->form != CHEM_PERSISTENT) return fail(CHEM_EUNSUPPORTED, "autotuning covers the persistent form");
+  if (n == 0) return CHEM_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int NY = M->m.n();
+  DevBuf ycopy, st;
+  chem_err e;
+  if ((e = ycopy.ensure(sizeof(double) * NY * static_cast<size_t>(ld)))) return e;
+  if ((e = st.ensure(sizeof(int) * static_cast<size_t>(ld)))) return e;
+  hipEvent_t a, b;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  const KernelId k = opts->method == CHEM_ROS2 ? K_ROS2_PERSISTENT : K_BE_PERSISTENT;
+  float best = 1e30f;
+  int best_block = 64, best_grid = 0;
+  const int method = opts->method;
+  for (int block : {64, 128, 256}) {
+    const int occ = occupancy_blocks(M, k, block);
+    for (int mult : {1, 2}) {
+      const int grid = occ * M->num_cu * mult;
+      if ((e = chem_set_launch(M, method, CHEM_PERSISTENT, block, grid))) break;
+      HIP_TRY(hipMemcpyAsync(ycopy.p, y, sizeof(double) * NY * static_cast<size_t>(ld), hipMemcpyDeviceToDevice, s));
+      HIP_TRY(hipEventRecord(a, s));
+      e = chem_integrate(M, n, ld, ycopy.as<double>(), lnA, opts, nullptr, st.as<int>(), nullptr, stream);
+      HIP_TRY(hipEventRecord(b, s));
+      HIP_TRY(hipEventSynchronize(b));
+      if (e) break;
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, a, b));
+      if (ms < best) {
+        best = ms;
+        best_block = block;
+        best_grid = grid;
+      }
+    }
+    if (e) break;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e) return e;
+  return chem_set_launch(M, method, CHEM_PERSISTENT, best_block, best_grid);
+}
+
+}  // extern "C"
