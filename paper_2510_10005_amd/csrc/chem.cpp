@@ -90,7 +90,15 @@ bool read_file(const std::string& p, std::string& out) {
 }
 
 std::vector<std::string> compile_options(const std::string& arch) {
-  return {"--offload-arch=" + arch, "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+  std::vector<std::string> o = {"--offload-arch=" + arch, "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                                "-packed-fp32-ops"};
+  // extra hipRTC flags (e.g. scheduler selection) for tuning experiments; part of the cache key
+  if (const char* extra = std::getenv("CHEM_HIPRTC_FLAGS")) {
+    std::istringstream ss(extra);
+    std::string tok;
+    while (ss >> tok) o.push_back(tok);
+  }
+  return o;
 }
 
 // generate + compile (or fetch from the cache); returns the code object bytes

@@ -49,7 +49,15 @@ static std::string conc_product(const std::vector<std::pair<int, int>>& side, in
   return out.empty() ? "1.0" : out;
 }
 
-static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool jac) {
+// Jacobian element reference for full state index (rf, cf): in the reduced (active-species)
+// system a column of a species that never changes is dropped; its rows are zero anyway.
+static std::string jref(int rf, int cf, const std::vector<int>& red) {
+  const int rr = red[rf], cr = red[cf];
+  return "J(RED ? " + std::to_string(rr) + " : " + std::to_string(rf) + ", RED ? " + std::to_string(cr) + " : " +
+         std::to_string(cf) + ")";
+}
+
+static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool jac, const std::vector<int>& red) {
   const Reaction& r = m.reactions[j];
   const std::string J = std::to_string(j);
   os << "  { // reaction " << j << ": " << r.equation << "\n";
@@ -177,18 +185,20 @@ static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool ja
   }
   for (auto& d : dq) os << "      const double dq" << d.first << " = " << d.second << ";\n";
   for (auto& p : nu) {
-    const std::string row = std::to_string(1 + p.first);
     const std::string nv = num(static_cast<double>(p.second));
-    auto acc = [&](const std::string& col, const std::string& val) {
+    auto acc = [&](int colf, const std::string& val) {
+      const int rowf = 1 + p.first;
+      const std::string ref = jref(rowf, colf, red);
+      const std::string guard = red[colf] < 0 ? "if (!RED) " : "";
       if (p.second == 1)
-        os << "      J(" << row << "," << col << ") += " << val << ";\n";
+        os << "      " << guard << ref << " += " << val << ";\n";
       else if (p.second == -1)
-        os << "      J(" << row << "," << col << ") -= " << val << ";\n";
+        os << "      " << guard << ref << " -= " << val << ";\n";
       else
-        os << "      J(" << row << "," << col << ") = fma(" << nv << ", " << val << ", J(" << row << "," << col << "));\n";
+        os << "      " << guard << ref << " = fma(" << nv << ", " << val << ", " << ref << ");\n";
     };
-    acc("0", "dqdT");
-    for (auto& d : dq) acc(std::to_string(1 + d.first), "dq" + std::to_string(d.first));
+    acc(0, "dqdT");
+    for (auto& d : dq) acc(1 + d.first, "dq" + std::to_string(d.first));
   }
   os << "    }\n";
 }
@@ -211,72 +221,116 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
   for (int i = 0; i < ns; ++i) os << (i ? ", " : "") << num(kR / m.species[i].W);
   os << "};\n";
 
-  // ---- thermo: NASA-7 in Horner form with the range chosen per T_mid (Table 1, n_p = 4)
-  std::set<double> tmids;
-  for (auto& s : m.species) tmids.insert(s.T_mid);
-  os << "__device__ __forceinline__ void mech_thermo(double T, double lnT, double invT, double (&cpR)[NS], "
-        "double (&hRT)[NS], double (&sR)[NS], double (&gRT)[NS], double (&dcpR)[NS]) {\n";
-  int ti = 0;
-  std::map<double, int> tidx;
-  for (double t : tmids) {
-    os << "  const bool hi" << ti << " = T >= " << num(t) << ";\n";
-    tidx[t] = ti++;
-  }
-  for (int i = 0; i < ns; ++i) {
-    const Species& s = m.species[i];
-    const std::string h = "hi" + std::to_string(tidx[s.T_mid]);
-    os << "  { // " << s.name << "\n";
-    for (int k = 0; k < 7; ++k)
-      os << "    const double a" << k << " = " << h << " ? " << num(s.hi[k]) << " : " << num(s.lo[k]) << ";\n";
-    os << "    cpR[" << i << "] = a0 + T*(a1 + T*(a2 + T*(a3 + T*a4)));\n";
-    os << "    hRT[" << i << "] = a0 + T*(a1*0.5 + T*(a2*(1.0/3.0) + T*(a3*0.25 + T*(a4*0.2)))) + a5*invT;\n";
-    os << "    sR[" << i << "] = a0*lnT + T*(a1 + T*(a2*0.5 + T*(a3*(1.0/3.0) + T*(a4*0.25)))) + a6;\n";
-    os << "    gRT[" << i << "] = hRT[" << i << "] - sR[" << i << "];\n";
-    os << "    dcpR[" << i << "] = a1 + T*(2.0*a2 + T*(3.0*a3 + T*(4.0*a4)));\n";
-    os << "  }\n";
-  }
-  os << "}\n";
+  // ---- thermo: NASA-7 (Table 1, n_p = 4) in Horner form; each lane selects the coefficient set of
+  // its range (T < T_mid: low, else high).  Variants return only what a caller needs.
+  std::map<double, std::vector<int>> groups;
+  for (int i = 0; i < ns; ++i) groups[m.species[i].T_mid].push_back(i);
+  // what: bit 1 = cp, 2 = h, 4 = s, 8 = g (needs h and s), 16 = dcp
+  auto emit_thermo = [&](const std::string& name, const std::string& params, int what) {
+    os << "__device__ __forceinline__ void " << name << "(" << params << ") {\n";
+    for (auto& g : groups) {
+      os << "  {\n    const bool hi = T >= " << num(g.first) << ";\n";
+      for (int i : g.second) {
+        const Species& s = m.species[i];
+        const std::string I = std::to_string(i);
+        os << "    { // " << s.name << "\n";
+        {  // select the coefficient set per lane, then Horner
+          auto a = [&](int k) { return std::string("(hi ? ") + num(s.hi[k]) + " : " + num(s.lo[k]) + ")"; };
+          if (what & 1) os << "      cpR[" << I << "] = " << a(0) << " + T*(" << a(1) << " + T*(" << a(2) << " + T*(" << a(3) << " + T*" << a(4) << ")));\n";
+          if (what & 2 || what & 8)
+            os << "      const double h_ = " << a(0) << " + T*(0.5*" << a(1) << " + T*((1.0/3.0)*" << a(2)
+               << " + T*(0.25*" << a(3) << " + T*(0.2*" << a(4) << ")))) + " << a(5) << "*invT;\n";
+          if (what & 2) os << "      hRT[" << I << "] = h_;\n";
+          if (what & 4 || what & 8)
+            os << "      const double s_ = " << a(0) << "*lnT + T*(" << a(1) << " + T*(0.5*" << a(2) << " + T*((1.0/3.0)*"
+               << a(3) << " + T*(0.25*" << a(4) << ")))) + " << a(6) << ";\n";
+          if (what & 4) os << "      sR[" << I << "] = s_;\n";
+          if (what & 8) os << "      gRT[" << I << "] = h_ - s_;\n";
+          if (what & 16) os << "      dcpR[" << I << "] = " << a(1) << " + T*(2.0*" << a(2) << " + T*(3.0*" << a(3) << " + T*(4.0*" << a(4) << ")));\n";
+        }
+        os << "    }\n";
+      }
+      os << "  }\n";
+    }
+    os << "}\n";
+  };
+  emit_thermo("mech_thermo", "double T, double lnT, double invT, double (&cpR)[NS], double (&hRT)[NS], "
+              "double (&sR)[NS], double (&gRT)[NS], double (&dcpR)[NS]", 1 | 2 | 4 | 8 | 16);
+  emit_thermo("mech_thermo_hg", "double T, double lnT, double invT, double (&hRT)[NS], double (&gRT)[NS]", 2 | 8);
+  emit_thermo("mech_thermo_g", "double T, double lnT, double invT, double (&gRT)[NS]", 8);
+  emit_thermo("mech_thermo_cp", "double T, double (&cpR)[NS], double (&dcpR)[NS]", 1 | 16);
+  emit_thermo("mech_thermo_hcp", "double T, double invT, double (&hRT)[NS], double (&cpR)[NS]", 1 | 2);
 
   bool any_pd = false;
   for (auto& r : m.reactions) any_pd = any_pd || r.kind != RxKind::Elementary;
+  // active state components: T and every species with a non-zero net coefficient somewhere
+  std::vector<int> red(n, -1);
+  std::vector<int> act;
+  std::vector<bool> sp_active(ns, false);
+  for (int j = 0; j < nr; ++j)
+    for (auto& p : m.net(j)) sp_active[p.first] = true;
+  red[0] = 0;
+  act.push_back(0);
+  for (int i = 0; i < ns; ++i)
+    if (sp_active[i]) {
+      red[1 + i] = static_cast<int>(act.size());
+      act.push_back(1 + i);
+    }
+  os << "#define NA " << act.size() << "\n";
+  os << "__device__ __forceinline__ constexpr int act_full(int a) {\n  constexpr int t[NA] = {";
+  for (size_t a = 0; a < act.size(); ++a) os << (a ? ", " : "") << act[a];
+  os << "};\n  return t[a];\n}\n";
 
   // ---- source terms and Jacobian
-  os << "template <bool JAC, class MAT>\n"
+  os << "// RED: J is the active-component system (NA x NA); otherwise the full NY x NY matrix\n";
+  os << "template <bool JAC, class MAT, bool RED = false>\n"
         "__device__ CHEM_EVAL_INLINE void mech_eval(const double (&y)[NY], const double* __restrict__ lnA, int energy,"
         " double (&S)[NY], MAT& J) {\n";
   os << "  const double T = y[0];\n  const double lnT = log(T);\n  const double invT = 1.0 / T;\n";
   os << "  double C[NS];\n#pragma unroll\n  for (int i = 0; i < NS; ++i) C[i] = y[1 + i];\n";
-  os << "  double cpR[NS], hRT[NS], sR[NS], gRT[NS], dcpR[NS];\n";
-  os << "  mech_thermo(T, lnT, invT, cpR, hRT, sR, gRT, dcpR);\n";
+  os << "  double hRT[NS], gRT[NS];\n";
+  os << "  if (JAC) mech_thermo_hg(T, lnT, invT, hRT, gRT); else mech_thermo_g(T, lnT, invT, gRT);\n";
   if (any_pd) os << "  double Mc = 0.0;\n#pragma unroll\n  for (int i = 0; i < NS; ++i) Mc += C[i];\n";
   os << "  double w[NS];\n#pragma unroll\n  for (int i = 0; i < NS; ++i) w[i] = 0.0;\n";
   if (any_pd) os << "  double tbr[NS];\n#pragma unroll\n  for (int i = 0; i < NS; ++i) tbr[i] = 0.0;\n";
-  os << "  if (JAC) {\n    CHEM_MUNROLL\n    for (int i = 0; i < NY; ++i) {\n      CHEM_MUNROLL\n"
-        "      for (int k = 0; k < NY; ++k) J(i, k) = 0.0;\n    }\n  }\n";
+  os << "  if (JAC) {\n    CHEM_MUNROLL\n    for (int i = 0; i < MAT::DIM; ++i) {\n      CHEM_MUNROLL\n"
+        "      for (int k = 0; k < MAT::DIM; ++k) J(i, k) = 0.0;\n    }\n  }\n";
   for (int j = 0; j < nr; ++j) {
-    emit_rate(os, m, j, true);
+    emit_rate(os, m, j, true, red);
     os << "  }\n";
   }
+  os << "  double cpR[NS], dcpR[NS];\n";
+  os << "  if (JAC) mech_thermo_cp(T, cpR, dcpR); else mech_thermo_hcp(T, invT, hRT, cpR);\n";
   os << "  const double off = energy ? 1.0 : 0.0;\n";
   os << "  double hw[NS], cw[NS], N = 0.0, D = 0.0;\n";
   os << "#pragma unroll\n  for (int i = 0; i < NS; ++i) {\n    hw[i] = hRT[i] - off;\n    cw[i] = cpR[i] - off;\n"
         "    N = fma(hw[i], w[i], N);\n    D = fma(C[i], cw[i], D);\n  }\n";
-  os << "  S[0] = -T * N / D;\n#pragma unroll\n  for (int i = 0; i < NS; ++i) S[1 + i] = w[i];\n";
+  os << "  const double invD = 1.0 / D;\n";
+  os << "  S[0] = -T * N * invD;\n#pragma unroll\n  for (int i = 0; i < NS; ++i) S[1 + i] = w[i];\n";
   os << "  if (JAC) {\n";
+  // dense part of the third-body/falloff derivatives: d[M]/dC_k = default efficiency
   if (any_pd) {
-    os << "    CHEM_MUNROLL\n    for (int i = 0; i < NS; ++i) {\n      CHEM_MUNROLL\n"
-          "      for (int k = 0; k < NS; ++k) J(1 + i, 1 + k) += tbr[i];\n    }\n";
+    for (int i = 0; i < ns; ++i) {
+      if (!sp_active[i]) continue;
+      for (int k = 0; k < ns; ++k) {
+        const std::string ref = jref(1 + i, 1 + k, red);
+        os << "    " << (red[1 + k] < 0 ? "if (!RED) " : "") << ref << " += tbr[" << i << "];\n";
+      }
+    }
   }
-  os << "    const double A = T * N / (D * D);\n";
+  os << "    const double A = T * N * invD * invD;\n";
   os << "    double s1 = 0.0, s2 = 0.0, s3 = 0.0;\n";
-  os << "#pragma unroll\n    for (int i = 0; i < NS; ++i) {\n      s1 = fma(cw[i], w[i], s1);\n"
-        "      s2 = fma(hw[i], J(1 + i, 0), s2);\n      s3 = fma(C[i], dcpR[i], s3);\n    }\n";
-  os << "    J(0, 0) = -(s1 + T * s2) / D + A * s3;\n";
-  os << "    CHEM_MUNROLL\n    for (int k = 0; k < NS; ++k) {\n      double t = 0.0;\n      CHEM_MUNROLL\n"
-        "      for (int i = 0; i < NS; ++i) t = fma(hw[i], J(1 + i, 1 + k), t);\n"
-        "      J(0, 1 + k) = -T * t / D + A * cw[k];\n    }\n";
-  os << "  }\n}\n";
-
+  os << "#pragma unroll\n    for (int i = 0; i < NS; ++i) {\n      s1 = fma(cw[i], w[i], s1);\n      s3 = fma(C[i], dcpR[i], s3);\n    }\n";
+  for (int i = 0; i < ns; ++i)
+    if (sp_active[i]) os << "    s2 = fma(hw[" << i << "], " << jref(1 + i, 0, red) << ", s2);\n";
+  os << "    " << jref(0, 0, red) << " = -(s1 + T * s2) * invD + A * s3;\n";
+  for (int k = 0; k < ns; ++k) {
+    os << "    " << (red[1 + k] < 0 ? "if (!RED) " : "") << "{\n      double t = 0.0;\n";
+    for (int i = 0; i < ns; ++i)
+      if (sp_active[i]) os << "      t = fma(hw[" << i << "], " << jref(1 + i, 1 + k, red) << ", t);\n";
+    os << "      " << jref(0, 1 + k, red) << " = -T * t * invD + A * cw[" << k << "];\n    }\n";
+  }
+  os << "  }\n}\n\n";
   // ---- d/d lnA contraction for the adjoint: g_j += q_j (sum_i nu_ij mu_i - mu_T T sum_i nu_ij hw_i / D)
   os << "template <class GACC>\n"
         "__device__ CHEM_EVAL_INLINE void mech_grad(const double (&y)[NY], const double* __restrict__ lnA, int energy,"
@@ -290,7 +344,7 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
         "#pragma unroll\n  for (int i = 0; i < NS; ++i) D = fma(C[i], cpR[i] - off, D);\n";
   os << "  const double muT = -T * mu[0] / D;\n";
   for (int j = 0; j < nr; ++j) {
-    emit_rate(os, m, j, false);
+    emit_rate(os, m, j, false, red);
     auto nu = m.net(j);
     os << "    const double dH = ";
     bool first = true;

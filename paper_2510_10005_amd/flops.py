@@ -109,6 +109,12 @@ class MechanismCounts:
         self.n = self.ns + 1
         self.rx = self.doc["reactions"]
         self.any_pd = any(r["type"] != "elementary" for r in self.rx)
+        active = set()
+        for r in self.rx:
+            active |= set(_net(r))
+        # integrators solve only T and the species that change (the others have zero increments)
+        self.ns_active = len(active)
+        self.na = self.ns_active + 1
 
     def source(self) -> Count:
         ns = self.ns
@@ -122,29 +128,31 @@ class MechanismCounts:
         c.flops += 6 * ns + 2                                       # omega_T
         return c
 
-    def jacobian(self) -> Count:
+    def jacobian(self, reduced: bool = False) -> Count:
+        """Full Jacobian (API kernel), or the active-component one the integrators factor."""
         ns = self.ns
+        cols = self.ns_active if reduced else ns
         c = Count(flops=1, tops=1)
         c.flops += 46 * ns
         if self.any_pd:
-            c.flops += ns - 1 + ns * ns                              # M_c, dense third-body part
+            c.flops += ns - 1 + self.ns_active * cols               # M_c, dense third-body part
         for r in self.rx:
             c = c + _rate_count(r, True)
         c.flops += 6 * ns + 2
-        c.flops += 3 + 6 * ns + 5 + ns * (2 * ns + 4)               # temperature row
+        c.flops += 3 + 4 * ns + 2 * self.ns_active + 5 + cols * (2 * self.ns_active + 4)   # temperature row
         return c
 
-    def lu(self) -> Count:
-        n = self.n
+    def lu(self, n=None) -> Count:
+        n = self.na if n is None else n
         return Count(flops=sum(1 + (n - k - 1) + 2 * (n - k - 1) ** 2 for k in range(n)))
 
-    def solve(self) -> Count:
-        n = self.n
+    def solve(self, n=None) -> Count:
+        n = self.na if n is None else n
         return Count(flops=2 * n * (n - 1) + n)
 
     def ros2_attempt(self) -> Count:
-        n, ns = self.n, self.ns
-        c = self.jacobian() + self.lu() + self.solve() * 2 + self.source()
+        n, ns = self.na, self.ns
+        c = self.jacobian(reduced=True) + self.lu() + self.solve() * 2 + self.source()
         c.flops += 2 + n                                            # 1/(gamma h), G = d I - J
         c.flops += 2 * n + 2 * n + 1                                # y*, rhs of stage 2
         c.flops += 4 * n + 2 * n                                    # y_new, error vector
@@ -154,8 +162,8 @@ class MechanismCounts:
         return c
 
     def be_iteration(self) -> Count:
-        n, ns = self.n, self.ns
-        c = self.jacobian() + self.lu() + self.solve()
+        n, ns = self.na, self.ns
+        c = self.jacobian(reduced=True) + self.lu() + self.solve()
         c.flops += 1 + 1 + n + 3 * n                                # h, 1/h, G, residual
         c.flops += n + 3 + 6 * ns                                   # update, scaled norm
         return c
