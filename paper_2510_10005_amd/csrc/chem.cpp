@@ -190,6 +190,7 @@ struct chem_tape {
 
 struct chem_mech {
   chem::Mechanism m;
+  int n_active = 0;  // T plus the species with a non-zero net coefficient (size of the solved system)
   int device = 0;
   int num_cu = 0;
   std::string arch;
@@ -259,10 +260,20 @@ chem_err validate_opts(const chem_integrator_opts* o) {
   return CHEM_OK;
 }
 
+// dynamic LDS of a launch: the Rosenbrock kernels park the upper LU factor of each lane
+// (register-resident mechanisms only)
+unsigned shmem_for(const chem_mech* M, KernelId k, int block) {
+  if (!M->dense || (k != K_ROS2_PERSISTENT && k != K_ROS2_STEP)) return 0;
+  const int na = M->n_active;
+  return static_cast<unsigned>(na * (na + 1) / 2) * static_cast<unsigned>(block) * sizeof(double);
+}
+
 // blocks per CU the runtime reports for a kernel at this block size (>= 1)
 int occupancy_blocks(const chem_mech* M, KernelId k, int block) {
   int nb = 0;
-  if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, M->fn[k], block, 0) != hipSuccess || nb < 1) nb = 1;
+  if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, M->fn[k], block, shmem_for(M, k, block)) != hipSuccess ||
+      nb < 1)
+    nb = 1;
   return nb;
 }
 
@@ -345,6 +356,12 @@ chem_err chem_load_mechanism(const char* path, const char* cache_dir, chem_mech*
   HIP_TRY(hipModuleLoadData(&M->module, code.data()));
   for (int k = 0; k < K_COUNT; ++k) HIP_TRY(hipModuleGetFunction(&M->fn[k], M->module, kKernelNames[k]));
   M->dense = M->m.n() <= kDenseLimit;
+  {
+    std::vector<bool> act(M->m.ns(), false);
+    for (int j = 0; j < M->m.nr(); ++j)
+      for (auto& p : M->m.net(j)) act[p.first] = true;
+    M->n_active = 1 + static_cast<int>(std::count(act.begin(), act.end(), true));
+  }
   std::vector<double> lnA(std::max(1, M->m.nr()), 0.0);
   for (int j = 0; j < M->m.nr(); ++j) lnA[j] = M->m.reactions[j].k.lnA;
   if ((e = M->lnA_default.ensure(lnA.size() * sizeof(double)))) return e;
@@ -510,7 +527,7 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
     if ((e = fill_u64(M, q, 1, 0, s))) return e;
     if (method == CHEM_ROS2) {
       void* args[] = {&n, &ld, &y, &la, &o, &status, &cnt, &q, &ws, &slots};
-      if ((e = launch(M, k, grid, block, s, args))) return e;
+      if ((e = launch(M, k, grid, block, s, args, shmem_for(M, k, block)))) return e;
     } else {
       void* args[] = {&n, &ld, &y, &la, &o, &status, &cnt, &q, &ws, &slots, &ckpt, &nsub};
       if ((e = launch(M, k, grid, block, s, args))) return e;
@@ -539,7 +556,7 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
         for (int b = 0; b < batch; ++b) {
           unsigned int* slot = run + b;
           void* args[] = {&n, &ld, &y, &la, &o, &status, &cnt, &wst, &slot, &ws, &slots};
-          if ((e = launch(M, K_ROS2_STEP, grid, block, s, args))) return e;
+          if ((e = launch(M, K_ROS2_STEP, grid, block, s, args, shmem_for(M, K_ROS2_STEP, block)))) return e;
         }
         launched += batch;
         HIP_TRY(hipMemcpyAsync(M->running_host, run + batch - 1, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
