@@ -45,6 +45,9 @@ def main():
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-adjoint", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-kernels", action="store_true")
+    ap.add_argument("--probe", type=int, default=None,
+                    help="probe_attempts of the persistent form (default: the library's)")
     ap.add_argument("--cpu-cells", type=int, default=24)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -76,7 +79,8 @@ def main():
     y = torch.empty_like(y0)
     status = torch.empty(n, dtype=torch.int32, device=dev)
     counters = torch.zeros((3, n), dtype=torch.int32, device=dev)
-    opts = default_options(method=CHEM_ROS2, dt=1e-6, n_steps=0, rtol=1e-6, atol=1e-10, form=CHEM_PERSISTENT)
+    probe = {} if args.probe is None else {"probe_attempts": args.probe}
+    opts = default_options(method=CHEM_ROS2, dt=1e-6, n_steps=0, rtol=1e-6, atol=1e-10, form=CHEM_PERSISTENT, **probe)
 
     if args.launch:
         b_, g_ = (int(v) for v in args.launch.split(","))
@@ -90,7 +94,7 @@ def main():
 
     def one_step(form):
         y.copy_(y0)
-        o = default_options(method=CHEM_ROS2, dt=1e-6, n_steps=0, rtol=1e-6, atol=1e-10, form=form)
+        o = default_options(method=CHEM_ROS2, dt=1e-6, n_steps=0, rtol=1e-6, atol=1e-10, form=form, **probe)
         gm.chem_integrate(n, n, y, None, o, None, status, counters)
 
     for _ in range(args.warmup):
@@ -125,11 +129,14 @@ def main():
     sub = counters[0].to(torch.float64)
     imbalance = float(sub.max().item() / max(1.0, sub.median().item()))
 
-    extras = {"persistent_launch": {"block": block, "grid": grid},
+    extras = {"persistent_launch": {"block": block, "grid": grid, "probe_attempts": opts.probe_attempts},
               "accepted_substeps_per_step": acc, "rejected_attempts_per_step": rej,
               "substep_max_over_median": imbalance, "failed_cells": n_fail,
               "flops_per_attempt": per_attempt.flops, "transcendentals_per_attempt": per_attempt.tops,
               "transcendentals_per_s": per_attempt.tops * att_total / (kernel_ms * 1e-3)}
+
+    if not args.skip_kernels:
+        extras["api_kernels"] = api_kernel_rates(gm, counts, y0, n, torch, dev)
 
     if not args.skip_plain:
         torch.cuda.synchronize()
@@ -174,6 +181,39 @@ def main():
         "extras": extras,
     }
     print(json.dumps(line), flush=True)
+
+
+def api_kernel_rates(gm, counts, y0, n, torch, dev, reps=5):
+    """Standalone source-term and Jacobian kernels over the same cells: event-timed per launch,
+    algorithmic FP64 rate against the vector peak and HBM bytes (state in, result out) against
+    the HBM peak."""
+    nn = gm.n
+    stream = torch.cuda.current_stream()
+    out = {}
+    src = torch.empty((nn, n), dtype=torch.float64, device=dev)
+    jac = torch.empty((nn * nn, n), dtype=torch.float64, device=dev)
+    cases = (("source_terms", lambda: gm.chem_source_terms(n, n, y0, None, 0, src), counts.source(), 2 * nn * 8),
+             ("jacobian", lambda: gm.chem_jacobian(n, n, y0, None, 0, jac), counts.jacobian(), (nn + nn * nn) * 8))
+    for name, fn, c, nbytes in cases:
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        sec = a.elapsed_time(b) * 1e-3 / reps
+        fl = c.flops * n / sec
+        bw = nbytes * n / sec
+        out[name] = {"ms_per_launch": sec * 1e3, "cells": n, "flops_per_cell": c.flops,
+                     "transcendentals_per_cell": c.tops, "tflops_algorithmic": fl / 1e12,
+                     "fp64_frac": fl / PEAK_FP64, "hbm_bytes_per_cell": nbytes, "hbm_gbs": bw / 1e9,
+                     "hbm_frac": bw / PEAK_HBM, "transcendentals_per_s": c.tops * n / sec}
+        log(f"{name}: {sec * 1e3:.3f} ms per launch, {fl / 1e12:.2f} TFLOP/s algorithmic ({fl / PEAK_FP64:.1%}), "
+            f"{bw / 1e9:.0f} GB/s ({bw / PEAK_HBM:.1%} of HBM)")
+    del src, jac
+    return out
 
 
 def adjoint_ratio(gm, torch, np, dev, Tape, default_options, CHEM_BE, sample_states, loss_weights, STATE_CONFIGS):

@@ -82,6 +82,12 @@ enum { CHEM_FLAG_CHECK_CELLS = 1 };  /* synchronise and return CHEM_ECELLS if a 
  *  Newton convergence: max_i |delta_i| / sc_i <= 1 with sc_T = newton_rtol T + newton_atol_T and,
  *  for species, sc = (newton_atol_Y + newton_rtol |Y_i|) rho / W_i; divergence: the scaled
  *  norm grows from the third iteration on.
+ *  probe_attempts  (CHEM_ROS2 + CHEM_PERSISTENT) > 0: the split step runs as a probe launch in
+ *           which each cell takes at most probe_attempts attempts, then a resume launch that
+ *           continues the unfinished cells, those with the most predicted remaining work first
+ *           (their first attempts' rate extrapolated), so that long cells do not start last.
+ *           The step sequence of every cell, and so every result, is the same as with 0 (one
+ *           launch).  Ignored for other methods and forms, and when n_cells >= 2^31.
  */
 typedef struct {
   int method;
@@ -99,11 +105,13 @@ typedef struct {
   double newton_rtol;
   double newton_atol_T;
   double newton_atol_Y;
+  int probe_attempts;
+  int reserved_;  /* padding; keep 0 */
 } chem_integrator_opts;
 
 /* Defaults: BE, const-p, persistent, dt 1e-7, n_steps 0, max_steps 100000, rtol 1e-6, atol 1e-10,
  * h_min 1e-20, newton_max 10, halving_max_depth 8, newton_rtol 1e-10, newton_atol_T 1e-8 K,
- * newton_atol_Y 1e-14. */
+ * newton_atol_Y 1e-14, probe_attempts 48. */
 void chem_default_options(chem_integrator_opts* opts);
 
 /* Human-readable name of an error code (static string, never NULL). */
@@ -125,7 +133,10 @@ chem_err chem_load_mechanism(const char* path, const char* cache_dir, chem_mech*
 void chem_free_mechanism(chem_mech* mech);
 
 /* Generate and compile the kernels of a mechanism file for gfx950 into cache_dir without needing
- * a GPU (the ahead-of-time step of the build).  Writes the code-object path to path_out. */
+ * a GPU (the ahead-of-time step of the build).  A mechanism whose state exceeds the register-
+ * resident limit (n > 24) is compiled as four programs (API kernels, Rosenbrock, backward Euler,
+ * adjoint) on concurrent threads.  Writes the code-object path(s) to path_out, separated by ';'
+ * (truncated to path_cap - 1 characters). */
 chem_err chem_precompile(const char* path, const char* cache_dir, char* path_out, size_t path_cap);
 
 /* Sizes: species, reactions, elements, state length n = ns + 1. */

@@ -48,6 +48,7 @@ class IntegratorOptions(ctypes.Structure):
         ("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("h_min", ctypes.c_double),
         ("newton_max", ctypes.c_int), ("halving_max_depth", ctypes.c_int),
         ("newton_rtol", ctypes.c_double), ("newton_atol_T", ctypes.c_double), ("newton_atol_Y", ctypes.c_double),
+        ("probe_attempts", ctypes.c_int), ("reserved_", ctypes.c_int),
     ]
 
 

@@ -23,7 +23,7 @@ SOURCES = ["chem.cpp", "codegen.cpp", "mechanism.cpp"]
 
 def build_library(verbose: bool = True) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc, "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
+    cmd = [hipcc, "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-Wall", "-Wno-unused-function",
            "-I", INCLUDE, "-I", CSRC, "-o", LIB + ".tmp"]
     cmd += [os.path.join(CSRC, s) for s in SOURCES]
     cmd += ["-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"]

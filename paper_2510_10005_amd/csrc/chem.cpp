@@ -17,6 +17,7 @@
 #include <sstream>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "mechanism.hpp"
@@ -45,12 +46,14 @@ const char* kKernelNames[] = {
     "chem_k_thermo",        "chem_k_source",           "chem_k_jacobian",         "chem_k_state_from_TPY",
     "chem_k_mass_fractions", "chem_k_state_from_TPY_vjp", "chem_k_mass_fractions_vjp", "chem_k_fill_u64",
     "chem_k_ros2_persistent", "chem_k_ros2_init",       "chem_k_ros2_step",        "chem_k_be_persistent",
-    "chem_k_be_init",       "chem_k_be_step",          "chem_k_be_adjoint",       "chem_k_reduce_blocks"};
+    "chem_k_be_init",       "chem_k_be_step",          "chem_k_be_adjoint",       "chem_k_reduce_blocks",
+    "chem_k_sched_scan",    "chem_k_sched_scatter"};
 enum KernelId {
   K_THERMO, K_SOURCE, K_JACOBIAN, K_TPY, K_MASSFRAC, K_TPY_VJP, K_MASSFRAC_VJP, K_FILL_U64,
   K_ROS2_PERSISTENT, K_ROS2_INIT, K_ROS2_STEP, K_BE_PERSISTENT, K_BE_INIT, K_BE_STEP, K_BE_ADJOINT,
-  K_REDUCE_BLOCKS, K_COUNT
+  K_REDUCE_BLOCKS, K_SCHED_SCAN, K_SCHED_SCATTER, K_COUNT
 };
+constexpr int kSchedBins = 256;  // CHEM_SCHED_BINS in the device code
 
 struct DevChemOpts {  // layout mirrors ChemOpts in the generated source
   double dt, rtol, atol, h_min;
@@ -101,22 +104,37 @@ std::vector<std::string> compile_options(const std::string& arch) {
   return o;
 }
 
-// generate + compile (or fetch from the cache); returns the code object bytes
-chem_err build_code_object(const chem::Mechanism& m, const std::string& arch, const std::string& cache_dir,
-                           std::string& code, std::string& cache_path) {
-  const std::string src = chem::generate_source(m, kDenseLimit);
+// Kernel groups (CHEM_IN_GROUP in the device code).  A register-resident mechanism is one program;
+// a larger one is split into one program per group, compiled concurrently, because its code is
+// large enough that a single compile is slow.
+constexpr int kGroups = 4;
+const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1};
+
+struct CodeObject {
+  std::string code, path;
+  chem_err err = CHEM_OK;
+  std::string msg;
+};
+
+// compile one program (group < 0: all kernels), or fetch it from the cache
+void build_one(const std::string& src, const std::string& arch, const std::string& cache_dir, int group,
+               CodeObject& out) {
   auto opts = compile_options(arch);
+  if (group >= 0) opts.push_back("-DCHEM_KGROUP=" + std::to_string(group));
   int rtc_major = 0, rtc_minor = 0;
   hiprtcVersion(&rtc_major, &rtc_minor);
   std::string key = src + "|" + std::to_string(rtc_major) + "." + std::to_string(rtc_minor);
   for (auto& o : opts) key += "|" + o;
   char name[64];
   std::snprintf(name, sizeof(name), "chem_%016llx.hsaco", static_cast<unsigned long long>(fnv1a(key)));
-  cache_path = cache_dir + "/" + name;
-  if (read_file(cache_path, code) && !code.empty()) return CHEM_OK;
+  out.path = cache_dir + "/" + name;
+  if (read_file(out.path, out.code) && !out.code.empty()) return;
   hiprtcProgram prog;
-  if (hiprtcCreateProgram(&prog, src.c_str(), "chem_mechanism.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
-    return fail(CHEM_ECOMPILE, "hiprtcCreateProgram failed");
+  if (hiprtcCreateProgram(&prog, src.c_str(), "chem_mechanism.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+    out.err = CHEM_ECOMPILE;
+    out.msg = "hiprtcCreateProgram failed";
+    return;
+  }
   std::vector<const char*> copts;
   for (auto& o : opts) copts.push_back(o.c_str());
   hiprtcResult rc = hiprtcCompileProgram(prog, static_cast<int>(copts.size()), copts.data());
@@ -127,20 +145,42 @@ chem_err build_code_object(const chem::Mechanism& m, const std::string& arch, co
     if (ls) hiprtcGetProgramLog(prog, &log[0]);
     hiprtcDestroyProgram(&prog);
     if (log.size() > 4000) log = log.substr(0, 4000) + "...";
-    return fail(CHEM_ECOMPILE, "hipRTC compile failed: " + log);
+    out.err = CHEM_ECOMPILE;
+    out.msg = "hipRTC compile failed: " + log;
+    return;
   }
   size_t cs = 0;
   hiprtcGetCodeSize(prog, &cs);
-  code.assign(cs, '\0');
-  hiprtcGetCode(prog, &code[0]);
+  out.code.assign(cs, '\0');
+  hiprtcGetCode(prog, &out.code[0]);
   hiprtcDestroyProgram(&prog);
   mkdirs(cache_dir);
-  const std::string tmp = cache_path + ".tmp" + std::to_string(static_cast<long>(getpid()));
+  const std::string tmp = out.path + ".tmp" + std::to_string(static_cast<long>(getpid())) + "_" +
+                          std::to_string(group + 1);
   {
     std::ofstream f(tmp, std::ios::binary);
-    f.write(code.data(), static_cast<std::streamsize>(code.size()));
+    f.write(out.code.data(), static_cast<std::streamsize>(out.code.size()));
   }
-  std::rename(tmp.c_str(), cache_path.c_str());
+  std::rename(tmp.c_str(), out.path.c_str());
+}
+
+// generate + compile (or fetch from the cache) the code objects of a mechanism: one entry for a
+// register-resident mechanism, kGroups entries otherwise
+chem_err build_code_objects(const chem::Mechanism& m, const std::string& arch, const std::string& cache_dir,
+                            std::vector<CodeObject>& objs) {
+  const std::string src = chem::generate_source(m, kDenseLimit);
+  const bool split = m.n() > kDenseLimit;
+  objs.assign(split ? kGroups : 1, CodeObject{});
+  if (!split) {
+    build_one(src, arch, cache_dir, -1, objs[0]);
+  } else {
+    std::vector<std::thread> th;
+    for (int g = 0; g < kGroups; ++g)
+      th.emplace_back([&, g] { build_one(src, arch, cache_dir, g, objs[g]); });
+    for (auto& t : th) t.join();
+  }
+  for (auto& o : objs)
+    if (o.err) return fail(o.err, o.msg);
   return CHEM_OK;
 }
 
@@ -194,17 +234,17 @@ struct chem_mech {
   int device = 0;
   int num_cu = 0;
   std::string arch;
-  hipModule_t module = nullptr;
+  std::vector<hipModule_t> modules;
   hipFunction_t fn[K_COUNT] = {};
   bool dense = true;
-  DevBuf lnA_default, queue, ws, wst, counters_internal, running, seg, gws, gpart;
+  DevBuf lnA_default, queue, ws, wst, counters_internal, running, seg, gws, gpart, sched, order;
   unsigned int* running_host = nullptr;
   int launch_block[2][2] = {{0, 0}, {0, 0}};  // [method][form]
   int launch_grid[2][2] = {{0, 0}, {0, 0}};
   std::mutex mu;
   ~chem_mech() {
     if (running_host) (void)hipHostFree(running_host);
-    if (module) (void)hipModuleUnload(module);
+    for (hipModule_t md : modules) (void)hipModuleUnload(md);
   }
 };
 
@@ -257,6 +297,7 @@ chem_err validate_opts(const chem_integrator_opts* o) {
   if (!(o->h_min >= 0.0)) return fail(CHEM_EINVAL, "h_min must be >= 0");
   if (o->newton_max < 1 || o->halving_max_depth < 0 || o->halving_max_depth > 30)
     return fail(CHEM_EINVAL, "newton_max >= 1 and 0 <= halving_max_depth <= 30 required");
+  if (o->probe_attempts < 0) return fail(CHEM_EINVAL, "probe_attempts must be >= 0");
   return CHEM_OK;
 }
 
@@ -306,6 +347,8 @@ void chem_default_options(chem_integrator_opts* o) {
   o->newton_rtol = 1e-10;
   o->newton_atol_T = 1e-8;
   o->newton_atol_Y = 1e-14;
+  o->probe_attempts = 48;
+  o->reserved_ = 0;
 }
 
 const char* chem_error_string(chem_err e) {
@@ -328,11 +371,13 @@ chem_err chem_precompile(const char* path, const char* cache_dir, char* path_out
   chem::Mechanism m;
   chem_err e = parse_file(path, m);
   if (e) return e;
-  std::string code, cpath;
-  e = build_code_object(m, "gfx950", cache_dir ? cache_dir : default_cache_dir(), code, cpath);
+  std::vector<CodeObject> objs;
+  e = build_code_objects(m, "gfx950", cache_dir ? cache_dir : default_cache_dir(), objs);
   if (e) return e;
   if (path_out && cap) {
-    std::strncpy(path_out, cpath.c_str(), cap - 1);
+    std::string paths;
+    for (auto& o : objs) paths += (paths.empty() ? "" : ";") + o.path;
+    std::strncpy(path_out, paths.c_str(), cap - 1);
     path_out[cap - 1] = '\0';
   }
   return CHEM_OK;
@@ -350,11 +395,18 @@ chem_err chem_load_mechanism(const char* path, const char* cache_dir, chem_mech*
   M->num_cu = prop.multiProcessorCount;
   std::string arch = prop.gcnArchName;
   M->arch = arch.substr(0, arch.find(':'));
-  std::string code, cpath;
-  e = build_code_object(M->m, M->arch, cache_dir ? cache_dir : default_cache_dir(), code, cpath);
+  std::vector<CodeObject> objs;
+  e = build_code_objects(M->m, M->arch, cache_dir ? cache_dir : default_cache_dir(), objs);
   if (e) return e;
-  HIP_TRY(hipModuleLoadData(&M->module, code.data()));
-  for (int k = 0; k < K_COUNT; ++k) HIP_TRY(hipModuleGetFunction(&M->fn[k], M->module, kKernelNames[k]));
+  for (auto& o : objs) {
+    hipModule_t md = nullptr;
+    HIP_TRY(hipModuleLoadData(&md, o.code.data()));
+    M->modules.push_back(md);
+  }
+  for (int k = 0; k < K_COUNT; ++k) {
+    hipModule_t md = M->modules[M->modules.size() == 1 ? 0 : kKernelGroup[k]];
+    HIP_TRY(hipModuleGetFunction(&M->fn[k], md, kKernelNames[k]));
+  }
   M->dense = M->m.n() <= kDenseLimit;
   {
     std::vector<bool> act(M->m.ns(), false);
@@ -526,8 +578,40 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
     uint64_t* q = M->queue.as<uint64_t>();
     if ((e = fill_u64(M, q, 1, 0, s))) return e;
     if (method == CHEM_ROS2) {
-      void* args[] = {&n, &ld, &y, &la, &o, &status, &cnt, &q, &ws, &slots};
-      if ((e = launch(M, k, grid, block, s, args, shmem_for(M, k, block)))) return e;
+      const unsigned shm = shmem_for(M, k, block);
+      int budget = opts->probe_attempts;
+      if (n >= (int64_t(1) << 31)) budget = 0;
+      double* wst = nullptr;
+      int* order = nullptr;
+      unsigned int* sched = nullptr;
+      if (budget > 0) {
+        // probe launch, bins of the parked cells, resume launch in that order (no host sync)
+        if ((e = M->wst.ensure(sizeof(double) * 4 * static_cast<size_t>(n)))) return e;
+        if ((e = M->order.ensure(sizeof(int) * static_cast<size_t>(n)))) return e;
+        // [0] parked count, [1, 1 + bins) bin counts, [1 + bins, 1 + 2 bins) bin offsets, 1 pad word
+        if ((e = M->sched.ensure(sizeof(unsigned int) * (2 + 2 * kSchedBins)))) return e;
+        wst = M->wst.as<double>();
+        order = M->order.as<int>();
+        sched = M->sched.as<unsigned int>();
+        if ((e = fill_u64(M, reinterpret_cast<uint64_t*>(sched), (2 + 2 * kSchedBins) / 2, 0, s))) return e;
+      }
+      const int* no_order = nullptr;
+      void* args[] = {&n, &ld, &y, &la, &o, &status, &cnt, &q, &ws, &slots, &budget, &wst, &no_order, &sched};
+      if ((e = launch(M, k, grid, block, s, args, shm))) return e;
+      if (budget > 0) {
+        {
+          void* a2[] = {&sched};
+          if ((e = launch(M, K_SCHED_SCAN, 1, kSchedBins, s, a2))) return e;
+        }
+        {
+          void* a3[] = {&n, &status, &wst, &sched, &order};
+          if ((e = launch(M, K_SCHED_SCATTER, blocks_for(n, 256), 256, s, a3))) return e;
+        }
+        if ((e = fill_u64(M, q, 1, 0, s))) return e;
+        int zero = 0;
+        void* a4[] = {&n, &ld, &y, &la, &o, &status, &cnt, &q, &ws, &slots, &zero, &wst, &order, &sched};
+        if ((e = launch(M, k, grid, block, s, a4, shm))) return e;
+      }
     } else {
       void* args[] = {&n, &ld, &y, &la, &o, &status, &cnt, &q, &ws, &slots, &ckpt, &nsub};
       if ((e = launch(M, k, grid, block, s, args))) return e;

@@ -49,3 +49,29 @@ def test_precompile_generated_kernels(tmp_path):
     with pytest.raises(b.ChemError) as e:
         b.precompile(str(bad), str(tmp_path))
     assert e.value.code == 3
+
+
+def test_options_struct_layout_matches_header(tmp_path):
+    """The ctypes mirror of chem_integrator_opts has the C compiler's offsets and size."""
+    from paper_2510_10005_amd._binding import IntegratorOptions
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f for f, _ in IntegratorOptions._fields_]
+    src = tmp_path / "layout.c"
+    body = "\n".join(f'  printf("{f} %zu\\n", offsetof(chem_integrator_opts, {f}));' for f in fields)
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"chem.h\"\nint main(void) {\n" + body +
+                   '\n  printf("sizeof %zu\\n", sizeof(chem_integrator_opts));\n  return 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                       check=True).stdout.splitlines())
+    for f in fields:
+        assert int(out[f]) == getattr(IntegratorOptions, f).offset, f
+    assert int(out["sizeof"]) == ctypes.sizeof(IntegratorOptions)
+    from paper_2510_10005_amd import _binding as b
+    if os.path.exists(os.path.join(ROOT, "paper_2510_10005_amd", "libchem.so")):
+        o = b.default_options()
+        assert o.probe_attempts == 48 and o.reserved_ == 0
