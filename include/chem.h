@@ -127,6 +127,12 @@ const char* chem_last_error_message(void);
  * current device's architecture with hipRTC.  Compiled code objects are cached in cache_dir (or
  * $CHEM_KERNEL_CACHE, else a per-user temp directory) keyed by a hash of the generated source
  * and the compiler options.  The current HIP device at load time is the one the mechanism runs on.
+ * State size n = species + 1 selects the kernel form: n <= 24 one cell per GPU lane with the
+ * Jacobian and its LU in registers; 24 < n <= 64 one cell per 64-lane wavefront (row i of the
+ * iteration matrix in lane i, reactions spread over the lanes, constants in generated tables);
+ * n > 64 is rejected with CHEM_EUNSUPPORTED.  In this version chem_integrate, chem_autotune and
+ * chem_integrate_adjoint return CHEM_EUNSUPPORTED for 24 < n <= 64 (the one-wavefront integrators
+ * are built but switched off); the other entry points serve every supported size.
  * On success *out owns the mechanism; release it with chem_free_mechanism.
  */
 chem_err chem_load_mechanism(const char* path, const char* cache_dir, chem_mech** out);

@@ -6,11 +6,14 @@
 // is emitted from the chain rules of each rate form (Section 4.2) with only the entries the
 // reaction touches.  Unlike ChemGen, ln A stays a runtime array (it is a differentiable
 // parameter), and the emitted code is device code for one cell per GPU lane.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <set>
 #include <sstream>
 #include <string>
+#include <type_traits>
+#include <vector>
 
 #include "mechanism.hpp"
 
@@ -21,6 +24,9 @@ static const char* kPrelude =
     ;
 static const char* kKernels =
 #include "device_kernels.inc"
+    ;
+static const char* kWave =
+#include "device_wave.inc"
     ;
 
 static std::string num(double v) {
@@ -203,6 +209,154 @@ static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool ja
   os << "    }\n";
 }
 
+// Constant tables of the one-wave-per-cell form (large mechanisms): reactions at positions sorted
+// by rate form (elementary, third-body, Lindemann, Troe, Troe with T**) so that a round of 64
+// lanes mostly runs one branch; species reaction lists (CSR over positions) for the gathers.
+template <class T>
+static void emit_array(std::ostringstream& os, const char* type, const char* name, const std::vector<T>& v) {
+  os << "static __device__ const " << type << " " << name << "[" << (v.empty() ? 1 : v.size()) << "] = {";
+  if (v.empty()) os << "0";
+  for (size_t i = 0; i < v.size(); ++i) {
+    if (i) os << ", ";
+    if constexpr (std::is_floating_point<T>::value)
+      os << num(v[i]);
+    else
+      os << v[i];
+  }
+  os << "};\n";
+}
+
+static void emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
+  const int ns = m.ns(), nr = m.nr();
+  auto kind_of = [&](const Reaction& r) {
+    if (r.kind == RxKind::Elementary) return 0;
+    if (r.kind == RxKind::ThirdBody) return 1;
+    if (!r.troe) return 2;
+    return r.troe_has_T2 ? 4 : 3;
+  };
+  std::vector<int> pos(nr);
+  for (int j = 0; j < nr; ++j) pos[j] = j;
+  std::stable_sort(pos.begin(), pos.end(),
+                   [&](int a, int b) { return kind_of(m.reactions[a]) < kind_of(m.reactions[b]); });
+  int MR = 1, MP = 1, MN = 1, ME = 1, MD = 1;
+  std::vector<std::vector<int>> dsp(nr);
+  for (int j = 0; j < nr; ++j) {
+    const Reaction& r = m.reactions[j];
+    MR = std::max(MR, static_cast<int>(r.reactants.size()));
+    MP = std::max(MP, static_cast<int>(r.products.size()));
+    MN = std::max(MN, static_cast<int>(m.net(j).size()));
+    ME = std::max(ME, static_cast<int>(r.eff.size()));
+    std::set<int> d;
+    for (auto& p : r.reactants) d.insert(p.first);
+    if (r.reversible)
+      for (auto& p : r.products) d.insert(p.first);
+    if (r.kind != RxKind::Elementary)
+      for (auto& e : r.eff) d.insert(e.first);
+    dsp[j].assign(d.begin(), d.end());
+    MD = std::max(MD, static_cast<int>(d.size()));
+  }
+  os << "#define WV_MR " << MR << "\n#define WV_MP " << MP << "\n#define WV_MN " << MN << "\n#define WV_ME " << ME
+     << "\n#define WV_MD " << MD << "\n";
+  std::vector<int> rx, kind, rev, rs, rc, ps, pc, nus, es, ds;
+  std::vector<double> b, th, fo, tr, dnu, nuv, deff, ev;
+  for (int p = 0; p < nr; ++p) {
+    const int j = pos[p];
+    const Reaction& r = m.reactions[j];
+    rx.push_back(j);
+    kind.push_back(kind_of(r));
+    rev.push_back(r.reversible ? 1 : 0);
+    b.push_back(r.k.b);
+    th.push_back(r.k.theta);
+    const bool fall = r.kind == RxKind::Falloff;
+    fo.push_back(fall ? r.k0.lnA - r.k.lnA : 0.0);
+    fo.push_back(fall ? r.k0.b - r.k.b : 0.0);
+    fo.push_back(fall ? r.k0.theta - r.k.theta : 0.0);
+    tr.push_back(r.troe ? r.troe_alpha : 0.0);
+    tr.push_back(r.troe ? 1.0 / r.troe_T3 : 0.0);
+    tr.push_back(r.troe ? 1.0 / r.troe_T1 : 0.0);
+    tr.push_back(r.troe && r.troe_has_T2 ? r.troe_T2 : 0.0);
+    deff.push_back(r.default_eff);
+    for (int i = 0; i < MR; ++i) {
+      const bool u = i < static_cast<int>(r.reactants.size());
+      rs.push_back(u ? r.reactants[i].first : -1);
+      rc.push_back(u ? r.reactants[i].second : 0);
+    }
+    for (int i = 0; i < MP; ++i) {
+      const bool u = i < static_cast<int>(r.products.size());
+      ps.push_back(u ? r.products[i].first : -1);
+      pc.push_back(u ? r.products[i].second : 0);
+    }
+    auto nu = m.net(j);
+    int dn = 0, i = 0;
+    for (auto& q : nu) {
+      nus.push_back(q.first);
+      nuv.push_back(static_cast<double>(q.second));
+      dn += q.second;
+      ++i;
+    }
+    for (; i < MN; ++i) {
+      nus.push_back(-1);
+      nuv.push_back(0.0);
+    }
+    dnu.push_back(static_cast<double>(dn));
+    i = 0;
+    if (r.kind != RxKind::Elementary)
+      for (auto& e : r.eff) {
+        es.push_back(e.first);
+        ev.push_back(e.second - r.default_eff);
+        ++i;
+      }
+    for (; i < ME; ++i) {
+      es.push_back(-1);
+      ev.push_back(0.0);
+    }
+    for (i = 0; i < MD; ++i) ds.push_back(i < static_cast<int>(dsp[j].size()) ? dsp[j][i] : -1);
+  }
+  emit_array(os, "int", "wv_rx", rx);
+  emit_array(os, "int", "wv_kind", kind);
+  emit_array(os, "int", "wv_rev", rev);
+  emit_array(os, "double", "wv_b", b);
+  emit_array(os, "double", "wv_th", th);
+  emit_array(os, "double", "wv_fo", fo);
+  emit_array(os, "double", "wv_tr", tr);
+  emit_array(os, "double", "wv_deff", deff);
+  emit_array(os, "double", "wv_dnu", dnu);
+  emit_array(os, "int", "wv_rs", rs);
+  emit_array(os, "int", "wv_rc", rc);
+  emit_array(os, "int", "wv_ps", ps);
+  emit_array(os, "int", "wv_pc", pc);
+  emit_array(os, "int", "wv_nus", nus);
+  emit_array(os, "double", "wv_nuv", nuv);
+  emit_array(os, "int", "wv_es", es);
+  emit_array(os, "double", "wv_ev", ev);
+  emit_array(os, "int", "wv_ds", ds);
+  // species s: positions p (ascending) with nu_sp != 0
+  std::vector<int> ptr(1, 0), sp_p;
+  std::vector<double> sp_v;
+  for (int s = 0; s < ns; ++s) {
+    for (int p = 0; p < nr; ++p) {
+      auto nu = m.net(pos[p]);
+      auto it = nu.find(s);
+      if (it != nu.end()) {
+        sp_p.push_back(p);
+        sp_v.push_back(static_cast<double>(it->second));
+      }
+    }
+    ptr.push_back(static_cast<int>(sp_p.size()));
+  }
+  emit_array(os, "int", "wv_sp_ptr", ptr);
+  emit_array(os, "int", "wv_sp_p", sp_p);
+  emit_array(os, "double", "wv_sp_v", sp_v);
+  std::vector<double> nasa, tmid;
+  for (int s = 0; s < ns; ++s) {
+    for (int c = 0; c < 7; ++c) nasa.push_back(m.species[s].lo[c]);
+    for (int c = 0; c < 7; ++c) nasa.push_back(m.species[s].hi[c]);
+    tmid.push_back(m.species[s].T_mid);
+  }
+  emit_array(os, "double", "wv_nasa", nasa);
+  emit_array(os, "double", "wv_tmid", tmid);
+}
+
 std::string generate_source(const Mechanism& m, int dense_limit) {
   std::ostringstream os;
   const int ns = m.ns(), nr = m.nr(), n = m.n();
@@ -280,6 +434,15 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
   os << "__device__ __forceinline__ constexpr int act_full(int a) {\n  constexpr int t[NA] = {";
   for (size_t a = 0; a < act.size(); ++a) os << (a ? ", " : "") << act[a];
   os << "};\n  return t[a];\n}\n";
+
+  const bool wave = n > dense_limit;
+  os << "#define CHEM_WAVE " << (wave ? 1 : 0) << "\n";
+  if (wave) {
+    emit_wave_tables(os, m);
+    os << kKernels;
+    os << kWave;
+    return os.str();
+  }
 
   // ---- source terms and Jacobian
   os << "// RED: J is the active-component system (NA x NA); otherwise the full NY x NY matrix\n";

@@ -75,3 +75,14 @@ def test_options_struct_layout_matches_header(tmp_path):
     if os.path.exists(os.path.join(ROOT, "paper_2510_10005_amd", "libchem.so")):
         o = b.default_options()
         assert o.probe_attempts == 48 and o.reserved_ == 0
+
+
+def test_mechanism_above_wave_limit_is_rejected():
+    """States of more than 64 components are refused at parse time (no code is generated)."""
+    from paper_2510_10005_amd import _binding as b
+    from synth import mechanism_file
+    lib = b.load()
+    path = mechanism_file("large_150_1000").encode()
+    buf = ctypes.create_string_buffer(4096)
+    assert lib.chem_precompile(path, None, buf, 4096) == 7       # CHEM_EUNSUPPORTED
+    assert b"at most 63 are supported" in lib.chem_last_error_message()
