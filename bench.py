@@ -179,12 +179,29 @@ def main():
                                "(rtol 1e-6, atol 1e-10) over one 1e-6 s split step, persistent work-queue kernel",
                    "cells": n, "mechanism": "h2like_10_27", "method": "ros2", "dt_s": 1e-6},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64, "traffic": None,
+                     "frac": achieved / PEAK_FP64, "traffic": measured_traffic(path),
                      "kernel": "chem_k_ros2_persistent", "kernel_ms_per_launch": kernel_ms / args.steps},
         "cpu_baseline": cpu,
         "extras": extras,
     }
     print(json.dumps(line), flush=True)
+
+
+def measured_traffic(mech_path):
+    """HBM bytes per split step of the integration kernel from the committed rocprofv3 record
+    (FETCH_SIZE and WRITE_SIZE, calibrated against a copy kernel), or None when the code object
+    in use is not the one that was profiled."""
+    from paper_2510_10005_amd._binding import precompile
+    rec_path = os.path.join(ROOT, "profiles", "ros2_persistent_h2like_1m_traffic.json")
+    if not os.path.exists(rec_path):
+        return None
+    with open(rec_path) as f:
+        rec = json.load(f)
+    current = os.path.basename(precompile(mech_path, KERNEL_CACHE))
+    if current != rec["code_object"]:
+        log(f"traffic: profiled code object {rec['code_object']} is not the current {current}; reporting null")
+        return None
+    return rec["bytes_per_step"]
 
 
 def api_kernel_rates(gm, counts, y0, n, torch, dev, reps=5):
