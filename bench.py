@@ -150,6 +150,8 @@ def main():
                                 "persistent_speedup": value / (acc_p / wp)}
         log(f"plain: {acc_p / wp:.3e} cell-substeps/s ({wp * 1e3:.1f} ms); persistent speedup {value / (acc_p / wp):.2f}x")
 
+    extras["be_1024"] = be_small_rate(gm, torch, np, dev, default_options, CHEM_BE, sample_states, STATE_CONFIGS)
+
     if not args.skip_adjoint:
         extras["adjoint"] = adjoint_ratio(gm, torch, np, dev, Tape, default_options, CHEM_BE, sample_states,
                                           loss_weights, STATE_CONFIGS)
@@ -235,6 +237,35 @@ def api_kernel_rates(gm, counts, y0, n, torch, dev, reps=5):
             f"{bw / 1e9:.0f} GB/s ({bw / PEAK_HBM:.1%} of HBM)")
     del src, jac
     return out
+
+
+def be_small_rate(gm, torch, np, dev, default_options, CHEM_BE, sample_states, STATE_CONFIGS):
+    """The 1,024-cell backward-Euler workload (200 steps of 1e-7 s, persistent form): a batch far
+    too small to fill the GPU, reported for completeness."""
+    cfg = STATE_CONFIGS["be_small"]
+    n = cfg.n_cells
+    T, p, Y = sample_states(gm.ns, n, cfg.seed, cfg.T_range, cfg.alpha, cfg.p)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    y0 = torch.empty((gm.n, n), dtype=torch.float64, device=dev)
+    gm.chem_state_from_TPY(n, n, t(T), t(p), t(Y.T), y0)
+    y = torch.empty_like(y0)
+    st = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt = torch.zeros((3, n), dtype=torch.int32, device=dev)
+    opts = default_options(method=CHEM_BE, dt=2e-5, n_steps=200)
+    best = 1e30
+    for _ in range(3):
+        y.copy_(y0)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        gm.chem_integrate(n, n, y, None, opts, None, st, cnt)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - a)
+    steps = int(cnt[0].sum().item())
+    r = {"workload": f"h2like_10_27, {n} cells, T0~U[1000,1500] K, Dirichlet(1), backward Euler 200 x 1e-7 s, persistent",
+         "ms": best * 1e3, "cell_substeps_per_s": steps / best, "newton_iterations": int(cnt[2].sum().item()),
+         "failed_cells": int((st != 0).sum().item())}
+    log(f"BE 1024 cells: {best * 1e3:.2f} ms, {steps / best:.3e} cell-substeps/s")
+    return r
 
 
 def adjoint_ratio(gm, torch, np, dev, Tape, default_options, CHEM_BE, sample_states, loss_weights, STATE_CONFIGS,
