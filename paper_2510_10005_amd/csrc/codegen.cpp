@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <set>
 #include <sstream>
+#include <stdexcept>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -345,8 +346,29 @@ static void emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
     ptr.push_back(static_cast<int>(sp_p.size()));
   }
   emit_array(os, "int", "wv_sp_ptr", ptr);
-  emit_array(os, "int", "wv_sp_p", sp_p);
-  emit_array(os, "double", "wv_sp_v", sp_v);
+  // gather entries, 16 bytes each: x = position | (nu & 255) << 16, y..z = the record species
+  // (s + 1, 0 = none) of that position, one byte each (MD <= 8)
+  if (MD > 8) throw std::runtime_error("more than 8 derivative-record species per reaction");
+  std::vector<unsigned> sp_e;
+  for (size_t i = 0; i < sp_p.size(); ++i) {
+    const int nu = static_cast<int>(sp_v[i]);
+    if (nu < -128 || nu > 127 || sp_p[i] > 65535) throw std::runtime_error("gather entry out of range");
+    const int j = pos[sp_p[i]];
+    unsigned w[4] = {static_cast<unsigned>(sp_p[i]) | (static_cast<unsigned>(nu & 255) << 16), 0u, 0u, 0u};
+    for (int d = 0; d < static_cast<int>(dsp[j].size()); ++d)
+      w[1 + d / 4] |= static_cast<unsigned>(dsp[j][d] + 1) << (8 * (d % 4));
+    sp_e.insert(sp_e.end(), w, w + 4);
+  }
+  if (sp_e.empty()) sp_e.assign(4, 0u);
+  os << "static __device__ const unsigned wv_sp_e[" << sp_e.size() << "] __attribute__((aligned(16))) = {";
+  for (size_t i = 0; i < sp_e.size(); ++i) os << (i ? ", " : "") << sp_e[i] << "u";
+  os << "};\n";
+  int maxc = 0;
+  for (auto& r : m.reactions) {
+    for (auto& q : r.reactants) maxc = std::max(maxc, q.second);
+    for (auto& q : r.products) maxc = std::max(maxc, q.second);
+  }
+  os << "#define WV_MAXC " << maxc << "\n";
   std::vector<double> nasa, tmid;
   for (int s = 0; s < ns; ++s) {
     for (int c = 0; c < 7; ++c) nasa.push_back(m.species[s].lo[c]);
