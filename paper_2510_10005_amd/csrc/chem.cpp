@@ -54,11 +54,11 @@ const char* kKernelNames[] = {
     "chem_k_mass_fractions", "chem_k_state_from_TPY_vjp", "chem_k_mass_fractions_vjp", "chem_k_fill_u64",
     "chem_k_ros2_persistent", "chem_k_ros2_init",       "chem_k_ros2_step",        "chem_k_be_persistent",
     "chem_k_be_init",       "chem_k_be_step",          "chem_k_be_adjoint",       "chem_k_reduce_blocks",
-    "chem_k_sched_scan",    "chem_k_sched_scatter"};
+    "chem_k_sched_scan",    "chem_k_sched_scatter",    "chem_k_jac_transpose"};
 enum KernelId {
   K_THERMO, K_SOURCE, K_JACOBIAN, K_TPY, K_MASSFRAC, K_TPY_VJP, K_MASSFRAC_VJP, K_FILL_U64,
   K_ROS2_PERSISTENT, K_ROS2_INIT, K_ROS2_STEP, K_BE_PERSISTENT, K_BE_INIT, K_BE_STEP, K_BE_ADJOINT,
-  K_REDUCE_BLOCKS, K_SCHED_SCAN, K_SCHED_SCATTER, K_COUNT
+  K_REDUCE_BLOCKS, K_SCHED_SCAN, K_SCHED_SCATTER, K_JAC_TRANSPOSE, K_COUNT
 };
 constexpr int kSchedBins = 256;  // CHEM_SCHED_BINS in the device code
 
@@ -117,7 +117,7 @@ std::vector<std::string> compile_options(const std::string& arch) {
 // a larger one is split into one program per group, compiled concurrently, because its code is
 // large enough that a single compile is slow.
 constexpr int kGroups = 4;
-const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1};
+const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1, 0};
 
 struct CodeObject {
   std::string code, path;
@@ -250,7 +250,7 @@ struct chem_mech {
   hipFunction_t fn[K_COUNT] = {};
   bool dense = true;
   bool wave = false;  // one cell per 64-lane wavefront (blocks of 64)
-  DevBuf lnA_default, queue, ws, wst, counters_internal, running, seg, gws, gpart, sched, order;
+  DevBuf lnA_default, queue, ws, wst, counters_internal, running, seg, gws, gpart, sched, order, jstage;
   unsigned int* running_host = nullptr;
   int launch_block[2][2] = {{0, 0}, {0, 0}};  // [method][form]
   int launch_grid[2][2] = {{0, 0}, {0, 0}};
@@ -267,6 +267,14 @@ chem_err launch(const chem_mech* M, KernelId k, unsigned grid, unsigned block, h
                 unsigned shmem = 0) {
   if (grid == 0) return CHEM_OK;
   hipError_t e = hipModuleLaunchKernel(M->fn[k], grid, 1, 1, block, 1, 1, shmem, s, args, nullptr);
+  if (e != hipSuccess) return fail(CHEM_EDEVICE, std::string("launch of ") + kKernelNames[k] + ": " + hipGetErrorString(e));
+  return CHEM_OK;
+}
+
+chem_err launch2d(const chem_mech* M, KernelId k, unsigned gx, unsigned gy, unsigned block, hipStream_t s,
+                  void** args) {
+  if (gx == 0 || gy == 0) return CHEM_OK;
+  hipError_t e = hipModuleLaunchKernel(M->fn[k], gx, gy, 1, block, 1, 1, 0, s, args, nullptr);
   if (e != hipSuccess) return fail(CHEM_EDEVICE, std::string("launch of ") + kKernelNames[k] + ": " + hipGetErrorString(e));
   return CHEM_OK;
 }
@@ -497,7 +505,32 @@ chem_err chem_jacobian(const chem_mech* M, int64_t n, int64_t ld, const double* 
   if (energy != CHEM_CONST_P && energy != CHEM_CONST_V) return fail(CHEM_EINVAL, "unknown energy mode");
   const double* la = lnA ? lnA : M->lnA_default.as<double>();
   void* args[] = {&n, &ld, &y, &la, &energy, &jac};
-  if (M->wave) return launch(M, K_JACOBIAN, static_cast<unsigned>(n), 64, static_cast<hipStream_t>(stream), args);
+  if (M->wave) {
+    // one wave per cell into a cell-major staging buffer, then a tiled transpose to the SoA
+    // layout; cells are processed in chunks so that the staging buffer stays bounded
+    const int64_t NN = static_cast<int64_t>(M->m.n()) * M->m.n();
+    const int64_t chunk = std::min<int64_t>(n, 32768);
+    if (n == 0) return CHEM_OK;
+    chem_mech* Mm = const_cast<chem_mech*>(M);
+    std::lock_guard<std::mutex> lock(Mm->mu);
+    if (chem_err e = Mm->jstage.ensure(sizeof(double) * static_cast<size_t>(chunk * NN))) return e;
+    double* stage = Mm->jstage.as<double>();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+      int64_t nc = std::min(chunk, n - c0);
+      {
+        void* a[] = {&nc, &ld, &y, &la, &energy, &stage, &c0};
+        if (chem_err e = launch(M, K_JACOBIAN, static_cast<unsigned>(nc), 64, s, a)) return e;
+      }
+      {
+        void* a[] = {&nc, &ld, &stage, &c0, &jac};
+        if (chem_err e = launch2d(M, K_JAC_TRANSPOSE, static_cast<unsigned>((NN + 63) / 64),
+                                  static_cast<unsigned>((nc + 63) / 64), 256, s, a))
+          return e;
+      }
+    }
+    return CHEM_OK;
+  }
   return launch(M, K_JACOBIAN, blocks_for(n, 256), 256, static_cast<hipStream_t>(stream), args);
 }
 
