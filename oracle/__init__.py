@@ -8,7 +8,8 @@ temperature source under constant volume (Section 3, eq.
 temperature_source) or constant pressure (Appendix B), the analytic
 source Jacobian (Section 3.2), backward Euler with Newton (Section 3.2)
 and the two-stage Rosenbrock scheme (Appendix A.3), plus forward and
-reverse sensitivities of the backward-Euler map.
+reverse sensitivities of the backward-Euler map and the discrete adjoint
+of the Rosenbrock map along its accepted step sequence.
 
 It exists to check the HIP library, never to stand in for it: only the
 test suite, the smoke check and the CPU-baseline leg of the benchmark may
@@ -33,4 +34,4 @@ from .integrate import (  # noqa: F401
     CELL_OK, CELL_NEWTON_FAIL, CELL_DT_UNDERFLOW, CELL_MAX_STEPS, CELL_NONFINITE, CELL_T_RANGE,
     IntegratorOptions, state_from_TPY, mass_fractions, integrate_be, integrate_ros2,
 )
-from .sensitivity import be_tangent, be_adjoint  # noqa: F401
+from .sensitivity import be_tangent, be_adjoint, ros2_replay, ros2_adjoint, ros2_adjoint_cell  # noqa: F401
