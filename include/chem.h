@@ -7,7 +7,7 @@
  * Arrhenius, third-body and Troe/Lindemann falloff rates and reverse rates from equilibrium
  * constants (Section 2.2), its analytic Jacobian (Section 3.2), and the implicit integration of
  * dy/dt = S(y) over one operator-split step (backward Euler with Newton, Section 3.2; two-stage
- * Rosenbrock, Appendix A.3), plus the discrete adjoint of the backward-Euler integration.
+ * Rosenbrock, Appendix A.3), plus the discrete adjoints of both integrations.
  *
  * Conventions shared by every call:
  *  - Units are SI with kmol: T [K], C [kmol/m^3], p [Pa], time [s].
@@ -189,9 +189,10 @@ chem_err chem_mass_fractions_vjp(const chem_mech* mech, int64_t n_cells, int64_t
  * Integrate every cell over one split step: y[n][ld] is read and overwritten with the final
  * state.  status [ld] (required) receives a CHEM_CELL_* code; counters (nullable) [3][ld]
  * receives accepted substeps (BE: completed full steps), rejected attempts and Newton
- * iterations.  A failed cell keeps its last accepted state.  tape (nullable, BE only) records
- * what chem_integrate_adjoint needs; it must have been created for >= n_cells cells and the
- * same options must be used.
+ * iterations.  A failed cell keeps its last accepted state.  tape (nullable) records what
+ * chem_integrate_adjoint needs; it must have been created for >= n_cells cells and for this
+ * method (chem_tape_create: CHEM_BE; chem_tape_create_ros2: CHEM_ROS2 in the persistent form),
+ * and the same options must be used by the adjoint call.
  */
 chem_err chem_integrate(const chem_mech* mech, int64_t n_cells, int64_t ld, double* y,
                         const double* lnA, const chem_integrator_opts* opts, chem_tape* tape,
@@ -200,14 +201,33 @@ chem_err chem_integrate(const chem_mech* mech, int64_t n_cells, int64_t ld, doub
 /* Tape for the backward-Euler discrete adjoint: the state is checkpointed every
  * checkpoint_every steps; the backward pass recomputes each segment from its checkpoint. */
 chem_err chem_tape_create(const chem_mech* mech, int64_t n_cells, int checkpoint_every, chem_tape** out);
+
+/* Tape for the discrete adjoint of the two-stage Rosenbrock method (Appendix A.3), n <= 24 only
+ * (CHEM_EUNSUPPORTED otherwise).  chem_integrate with method CHEM_ROS2, the persistent form and
+ * this tape records the initial states and the step size of every accepted step (8 B per step
+ * and cell), on the device, allocated by that call; chem_integrate_adjoint rebuilds a checkpoint
+ * every checkpoint_every accepted steps (8 n B per checkpoint and cell, in the tape) by replaying
+ * the recorded steps.  A cell that needs more than max_steps accepted steps stops with
+ * CHEM_CELL_MAX_STEPS.  The step-size controller is not differentiated: the adjoint is that of the
+ * recorded step sequence. */
+chem_err chem_tape_create_ros2(const chem_mech* mech, int64_t n_cells, int max_steps, int checkpoint_every,
+                               chem_tape** out);
 void chem_tape_free(chem_tape* tape);
 
 /*
- * Discrete adjoint of the recorded backward-Euler integration.  Given dL/dy_N [n][ld] at the
- * final state, writes dL/dy_0 [n][ld] and dL/dlnA [nr] (summed over cells, deterministic order).
- * Every accepted (sub)step y -> y' with step h contributes
+ * Discrete adjoint of the recorded integration.  Given dL/dy_N [n][ld] at the final state, writes
+ * dL/dy_0 [n][ld] and dL/dlnA [nr] (summed over cells, deterministic order).  Cells whose forward
+ * status was not CHEM_CELL_OK get dL/dy_0 = 0 and add nothing to dL/dlnA.  Uses the same lnA as
+ * the forward run.
+ * Backward Euler: every accepted (sub)step y -> y' with step h contributes
  *   (I/h - J(y'))^T mu = lambda',  lambda = mu / h,  dL/dlnA_j += q_j(y') (sum_i nu_ij mu_i + mu_T dwT_j)
- * where dwT_j is d omega_T / d lnA_j per unit q_j.  Uses the same lnA as the forward run.
+ * where dwT_j is d omega_T / d lnA_j per unit q_j.
+ * Rosenbrock: every recorded step y -> y + m1 g1 + m2 g2 with G = I/(gamma h) - J(y) and
+ * y* = y + alpha g1 contributes (lambda = dL/dy' on entry, dL/dy on exit)
+ *   G^T u2 = m2 lambda,  G^T u1 = m1 lambda + alpha J(y*)^T u2 + (beta/h) u2,
+ *   lambda <- lambda + J(y)^T u1 + J(y*)^T u2 + (J'(y)[g1])^T u1 + (J'(y)[g2])^T u2,
+ *   dL/dlnA += u1^T (dS/dlnA(y) + (dS/dlnA)'(y)[g1]) + u2^T (dS/dlnA(y*) + (dS/dlnA)'(y)[g2])
+ * (F'(y)[v]: derivative along v, evaluated with dual numbers).
  */
 chem_err chem_integrate_adjoint(const chem_mech* mech, chem_tape* tape, const double* lnA,
                                 const double* dL_dyN, double* dL_dy0, double* dL_dlnA, void* stream);

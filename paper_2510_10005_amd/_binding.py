@@ -27,8 +27,8 @@ EXPORTED = [
     "chem_free_mechanism", "chem_precompile", "chem_mechanism_info", "chem_molecular_weights",
     "chem_default_lnA", "chem_thermo", "chem_source_terms", "chem_jacobian", "chem_state_from_TPY",
     "chem_mass_fractions", "chem_state_from_TPY_vjp", "chem_mass_fractions_vjp", "chem_integrate",
-    "chem_tape_create", "chem_tape_free", "chem_integrate_adjoint", "chem_set_launch", "chem_get_launch",
-    "chem_autotune",
+    "chem_tape_create", "chem_tape_create_ros2", "chem_tape_free", "chem_integrate_adjoint", "chem_set_launch",
+    "chem_get_launch", "chem_autotune",
 ]
 
 
@@ -94,6 +94,7 @@ def load():
     lib.chem_mass_fractions_vjp.argtypes = [_P, _I64, _I64, _P, _P, _P, _P, _P]
     lib.chem_integrate.argtypes = [_P, _I64, _I64, _P, _P, ctypes.POINTER(IntegratorOptions), _P, _P, _P, _P]
     lib.chem_tape_create.argtypes = [_P, _I64, _I, ctypes.POINTER(_P)]
+    lib.chem_tape_create_ros2.argtypes = [_P, _I64, _I, _I, ctypes.POINTER(_P)]
     lib.chem_tape_free.argtypes = [_P]
     lib.chem_tape_free.restype = None
     lib.chem_integrate_adjoint.argtypes = [_P, _P, _P, _P, _P, _P, _P]
@@ -221,10 +222,20 @@ class Mechanism:
 
 
 class Tape:
-    def __init__(self, mech: Mechanism, n_cells: int, checkpoint_every: int):
+    """Adjoint tape.  Backward Euler: Tape(mech, n_cells, checkpoint_every).  Rosenbrock:
+    Tape(mech, n_cells, checkpoint_every, method=CHEM_ROS2, max_steps=...)."""
+
+    def __init__(self, mech: Mechanism, n_cells: int, checkpoint_every: int, method: int = CHEM_BE,
+                 max_steps: int = 0):
         self.lib = mech.lib
+        self.method = method
         h = _P()
-        _check(self.lib.chem_tape_create(mech.handle, n_cells, checkpoint_every, ctypes.byref(h)), "chem_tape_create")
+        if method == CHEM_ROS2:
+            _check(self.lib.chem_tape_create_ros2(mech.handle, n_cells, max_steps, checkpoint_every, ctypes.byref(h)),
+                   "chem_tape_create_ros2")
+        else:
+            _check(self.lib.chem_tape_create(mech.handle, n_cells, checkpoint_every, ctypes.byref(h)),
+                   "chem_tape_create")
         self.handle = h
         self.mech = mech   # keeps the mechanism alive while the tape exists
 

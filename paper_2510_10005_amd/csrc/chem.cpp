@@ -54,12 +54,15 @@ const char* kKernelNames[] = {
     "chem_k_mass_fractions", "chem_k_state_from_TPY_vjp", "chem_k_mass_fractions_vjp", "chem_k_fill_u64",
     "chem_k_ros2_persistent", "chem_k_ros2_init",       "chem_k_ros2_step",        "chem_k_be_persistent",
     "chem_k_be_init",       "chem_k_be_step",          "chem_k_be_adjoint",       "chem_k_reduce_blocks",
-    "chem_k_sched_scan",    "chem_k_sched_scatter",    "chem_k_jac_transpose"};
+    "chem_k_sched_scan",    "chem_k_sched_scatter",    "chem_k_jac_transpose",    "chem_k_ros2_persistent_rec",
+    "chem_k_ros2_adjoint"};
 enum KernelId {
   K_THERMO, K_SOURCE, K_JACOBIAN, K_TPY, K_MASSFRAC, K_TPY_VJP, K_MASSFRAC_VJP, K_FILL_U64,
   K_ROS2_PERSISTENT, K_ROS2_INIT, K_ROS2_STEP, K_BE_PERSISTENT, K_BE_INIT, K_BE_STEP, K_BE_ADJOINT,
-  K_REDUCE_BLOCKS, K_SCHED_SCAN, K_SCHED_SCATTER, K_JAC_TRANSPOSE, K_COUNT
+  K_REDUCE_BLOCKS, K_SCHED_SCAN, K_SCHED_SCATTER, K_JAC_TRANSPOSE, K_ROS2_PERSISTENT_REC, K_ROS2_ADJOINT, K_COUNT
 };
+// kernels that only the register-resident form (n <= kDenseLimit) has
+bool dense_only(int k) { return k == K_ROS2_PERSISTENT_REC || k == K_ROS2_ADJOINT; }
 constexpr int kSchedBins = 256;  // CHEM_SCHED_BINS in the device code
 
 struct DevChemOpts {  // layout mirrors ChemOpts in the generated source
@@ -117,7 +120,7 @@ std::vector<std::string> compile_options(const std::string& arch) {
 // a larger one is split into one program per group, compiled concurrently, because its code is
 // large enough that a single compile is slow.
 constexpr int kGroups = 4;
-const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1, 0};
+const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1, 0, 1, 3};
 
 struct CodeObject {
   std::string code, path;
@@ -231,12 +234,14 @@ struct DevBuf {
 
 struct chem_tape {
   const chem_mech* mech = nullptr;
+  int method = CHEM_BE;  // integrator the tape records
   int64_t n_cells = 0;
   int64_t ld = 0;
   int ckpt_every = 1;
+  int max_steps = 0;     // Rosenbrock: accepted steps recorded per cell
   bool recorded = false;
   DevChemOpts opts{};
-  DevBuf ckpt, nsub, status;
+  DevBuf ckpt, nsub, status, hs, nacc;
   int ckpt_slots = 0, nsub_steps = 0;
 };
 
@@ -333,7 +338,7 @@ chem_err validate_opts(const chem_integrator_opts* o) {
 // dynamic LDS of a launch: the Rosenbrock kernels park the upper LU factor of each lane
 // (register-resident mechanisms only)
 unsigned shmem_for(const chem_mech* M, KernelId k, int block) {
-  if (!M->dense || (k != K_ROS2_PERSISTENT && k != K_ROS2_STEP)) return 0;
+  if (!M->dense || (k != K_ROS2_PERSISTENT && k != K_ROS2_PERSISTENT_REC && k != K_ROS2_STEP)) return 0;
   const int na = M->n_active;
   return static_cast<unsigned>(na * (na + 1) / 2) * static_cast<unsigned>(block) * sizeof(double);
 }
@@ -433,12 +438,13 @@ chem_err chem_load_mechanism(const char* path, const char* cache_dir, chem_mech*
     HIP_TRY(hipModuleLoadData(&md, o.code.data()));
     M->modules.push_back(md);
   }
+  M->dense = M->m.n() <= kDenseLimit;
+  M->wave = !M->dense;
   for (int k = 0; k < K_COUNT; ++k) {
+    if (M->wave && dense_only(k)) continue;
     hipModule_t md = M->modules[M->modules.size() == 1 ? 0 : kKernelGroup[k]];
     HIP_TRY(hipModuleGetFunction(&M->fn[k], md, kKernelNames[k]));
   }
-  M->dense = M->m.n() <= kDenseLimit;
-  M->wave = !M->dense;
   {
     std::vector<bool> act(M->m.ns(), false);
     for (int j = 0; j < M->m.nr(); ++j)
@@ -576,6 +582,21 @@ chem_err chem_tape_create(const chem_mech* M, int64_t n_cells, int ckpt_every, c
   return CHEM_OK;
 }
 
+chem_err chem_tape_create_ros2(const chem_mech* M, int64_t n_cells, int max_steps, int ckpt_every, chem_tape** out) {
+  if (!M || !out) return fail(CHEM_EINVAL, "null argument");
+  if (n_cells < 0 || max_steps < 1 || ckpt_every < 1)
+    return fail(CHEM_EINVAL, "n_cells >= 0, max_steps >= 1 and checkpoint_every >= 1 required");
+  if (M->wave) return fail(CHEM_EUNSUPPORTED, kWaveIntegrationOff);
+  chem_tape* t = new chem_tape();
+  t->mech = M;
+  t->method = CHEM_ROS2;
+  t->n_cells = n_cells;
+  t->max_steps = max_steps;
+  t->ckpt_every = ckpt_every;
+  *out = t;
+  return CHEM_OK;
+}
+
 void chem_tape_free(chem_tape* t) { delete t; }
 
 static chem_err fill_u64(chem_mech* M, uint64_t* p, int n, uint64_t v, hipStream_t s) {
@@ -592,9 +613,11 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
   if (chem_err e = validate_opts(opts)) return e;
   if (M->wave) return fail(CHEM_EUNSUPPORTED, kWaveIntegrationOff);
   if (tape) {
-    if (opts->method != CHEM_BE) return fail(CHEM_EUNSUPPORTED, "the adjoint tape is implemented for backward Euler");
     if (tape->mech != M) return fail(CHEM_EINVAL, "tape belongs to another mechanism");
+    if (tape->method != opts->method) return fail(CHEM_EINVAL, "tape was created for another method");
     if (tape->n_cells < n) return fail(CHEM_EINVAL, "tape was created for fewer cells");
+    if (tape->method == CHEM_ROS2 && opts->form != CHEM_PERSISTENT)
+      return fail(CHEM_EUNSUPPORTED, "Rosenbrock recording runs in the persistent form");
   }
   if (n == 0) return CHEM_OK;
   std::lock_guard<std::mutex> lock(M->mu);
@@ -610,7 +633,27 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
   }
   double* ckpt = nullptr;
   unsigned short* nsub = nullptr;
-  if (tape) {
+  double* hs = nullptr;
+  int* nacc = nullptr;
+  int cap = 0;
+  if (tape && tape->method == CHEM_ROS2) {
+    // step sizes of up to max_steps accepted steps, states every ckpt_every steps
+    cap = tape->max_steps;
+    const int slots = cap / o.ckpt_every + 1;
+    if ((e = tape->ckpt.ensure(sizeof(double) * static_cast<size_t>(slots) * NY * ld))) return e;
+    if ((e = tape->hs.ensure(sizeof(double) * static_cast<size_t>(cap) * ld))) return e;
+    if ((e = tape->nacc.ensure(sizeof(int) * static_cast<size_t>(ld)))) return e;
+    if ((e = tape->status.ensure(sizeof(int) * static_cast<size_t>(ld)))) return e;
+    ckpt = tape->ckpt.as<double>();
+    hs = tape->hs.as<double>();
+    nacc = tape->nacc.as<int>();
+    // initial states = checkpoint 0 (same [n][ld] layout); the adjoint rebuilds the others
+    HIP_TRY(hipMemcpyAsync(ckpt, y, sizeof(double) * static_cast<size_t>(NY) * ld, hipMemcpyDeviceToDevice, s));
+    tape->ld = ld;
+    tape->n_cells = n;
+    tape->opts = o;
+    tape->recorded = false;
+  } else if (tape) {
     const int slots = o.n_steps / o.ckpt_every + 1;
     if ((e = tape->ckpt.ensure(sizeof(double) * static_cast<size_t>(slots) * NY * ld))) return e;
     if ((e = tape->nsub.ensure(sizeof(unsigned short) * static_cast<size_t>(o.n_steps) * ld))) return e;
@@ -624,7 +667,7 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
   }
   const int method = opts->method;
   if (opts->form == CHEM_PERSISTENT) {
-    const KernelId k = method == CHEM_ROS2 ? K_ROS2_PERSISTENT : K_BE_PERSISTENT;
+    const KernelId k = method == CHEM_ROS2 ? (hs ? K_ROS2_PERSISTENT_REC : K_ROS2_PERSISTENT) : K_BE_PERSISTENT;
     int block;
     unsigned grid;
     persistent_config(M, method, k, block, grid);
@@ -655,7 +698,8 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
         if ((e = fill_u64(M, reinterpret_cast<uint64_t*>(sched), (2 + 2 * kSchedBins) / 2, 0, s))) return e;
       }
       const int* no_order = nullptr;
-      void* args[] = {&n, &ld, &y, &la, &o, &status, &cnt, &q, &ws, &slots, &budget, &wst, &no_order, &sched};
+      void* args[] = {&n,   &ld,       &y,     &la, &o,    &status, &cnt, &q, &ws, &slots, &budget,
+                      &wst, &no_order, &sched, &hs, &nacc, &cap};
       if ((e = launch(M, k, grid, block, s, args, shm))) return e;
       if (budget > 0) {
         {
@@ -668,7 +712,8 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
         }
         if ((e = fill_u64(M, q, 1, 0, s))) return e;
         int zero = 0;
-        void* a4[] = {&n, &ld, &y, &la, &o, &status, &cnt, &q, &ws, &slots, &zero, &wst, &order, &sched};
+        void* a4[] = {&n, &ld, &y, &la, &o, &status, &cnt, &q, &ws, &slots, &zero, &wst, &order, &sched,
+                      &hs, &nacc, &cap};
         if ((e = launch(M, k, grid, block, s, a4, shm))) return e;
       }
     } else {
@@ -731,6 +776,36 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
   return CHEM_OK;
 }
 
+// Reverse sweep of a Rosenbrock tape: one lane per cell (static grid-stride mapping), segment
+// states in M->seg, per-block ln A partial sums reduced in block order.
+static chem_err ros2_adjoint(chem_mech* M, chem_tape* tape, const double* la, const double* dLdyN, double* dLdy0,
+                             double* dLdlnA, hipStream_t s) {
+  int64_t n = tape->n_cells, ld = tape->ld;
+  const int NY = M->m.n(), NR = std::max(1, M->m.nr());
+  const int block = 256;
+  const unsigned cap = static_cast<unsigned>(occupancy_blocks(M, K_ROS2_ADJOINT, block) * M->num_cu);
+  const unsigned grid = std::max(1u, std::min(blocks_for(n, block), cap));
+  int64_t total = static_cast<int64_t>(grid) * block;
+  chem_err e;
+  const int K = tape->opts.ckpt_every;
+  if ((e = M->seg.ensure(sizeof(double) * static_cast<size_t>(K) * NY * total))) return e;
+  if ((e = M->gpart.ensure(sizeof(double) * static_cast<size_t>(grid) * NR))) return e;
+  DevChemOpts o = tape->opts;
+  const int* st = tape->status.as<int>();
+  const int* na = tape->nacc.as<int>();
+  const double* hs = tape->hs.as<double>();
+  double* ck = tape->ckpt.as<double>();
+  double* seg = M->seg.as<double>();
+  double* gp = M->gpart.as<double>();
+  {
+    void* args[] = {&n, &ld, &la, &o, &st, &na, &hs, &ck, &dLdyN, &dLdy0, &gp, &seg, &total};
+    if ((e = launch(M, K_ROS2_ADJOINT, grid, block, s, args))) return e;
+  }
+  int nb = static_cast<int>(grid);
+  void* args[] = {&nb, &gp, &dLdlnA};
+  return launch(M, K_REDUCE_BLOCKS, blocks_for(NR, 64), 64, s, args);
+}
+
 chem_err chem_integrate_adjoint(const chem_mech* Mc, chem_tape* tape, const double* lnA, const double* dLdyN,
                                 double* dLdy0, double* dLdlnA, void* stream) {
   chem_mech* M = const_cast<chem_mech*>(Mc);
@@ -743,6 +818,7 @@ chem_err chem_integrate_adjoint(const chem_mech* Mc, chem_tape* tape, const doub
   int64_t n = tape->n_cells, ld = tape->ld;
   const double* la = lnA ? lnA : M->lnA_default.as<double>();
   const int NY = M->m.n(), NR = std::max(1, M->m.nr());
+  if (tape->method == CHEM_ROS2) return ros2_adjoint(M, tape, la, dLdyN, dLdy0, dLdlnA, s);
   const int block = M->wave ? 64 : 256;
   const unsigned cap = static_cast<unsigned>(occupancy_blocks(M, K_BE_ADJOINT, block) * M->num_cu);
   const unsigned grid = std::max(1u, std::min(M->wave ? static_cast<unsigned>(std::min<int64_t>(n, 1 << 30))

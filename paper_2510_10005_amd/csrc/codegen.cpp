@@ -64,19 +64,25 @@ static std::string jref(int rf, int cf, const std::vector<int>& red) {
          std::to_string(cf) + ")";
 }
 
-static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool jac, const std::vector<int>& red) {
+// One reaction's rate (kf, kr, q).  jac: also its production-rate and Jacobian contributions
+// (mech_eval).  vjp: generic value type R and, instead of Jacobian entries, the contraction
+// with the adjoint weights of mech_vjp: sig = sum_i nu_ij ut_i, g_j += q sig, v_k += sig dq/dy_k
+// (the default-efficiency part of d[M]/dC goes to tbs, added to every species column at the end).
+static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool jac, const std::vector<int>& red,
+                      bool vjp = false) {
   const Reaction& r = m.reactions[j];
   const std::string J = std::to_string(j);
+  const std::string ty = vjp ? "R" : "double";
   os << "  { // reaction " << j << ": " << r.equation << "\n";
   // ln k = ln A + b ln T - (Ea/R) / T   (log form of the Arrhenius law, Section 2.2.1)
-  os << "    const double lnk = lnA[" << J << "]";
+  os << "    const " << ty << " lnk = lnA[" << J << "]";
   if (r.k.b != 0.0) os << " + " << num(r.k.b) << "*lnT";
   if (r.k.theta != 0.0) os << " - " << num(r.k.theta) << "*invT";
   os << ";\n";
   const bool pd = r.kind != RxKind::Elementary;
   if (pd) {
     // [M] = default * M_c + sum over listed species of (alpha - default) C_i
-    os << "    const double M = ";
+    os << "    const " << ty << " M = ";
     if (r.default_eff == 1.0)
       os << "Mc";
     else if (r.default_eff == 0.0)
@@ -87,13 +93,13 @@ static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool ja
     os << ";\n";
   }
   if (r.kind == RxKind::Elementary) {
-    os << "    const double kf = exp(lnk);\n";
+    os << "    const " << ty << " kf = exp(lnk);\n";
   } else if (r.kind == RxKind::ThirdBody) {
-    os << "    const double kf = M*exp(lnk);\n";
+    os << "    const " << ty << " kf = M*exp(lnk);\n";
   } else {
     const double db = r.k0.b - r.k.b, dth = r.k0.theta - r.k.theta, dlnA = r.k0.lnA - r.k.lnA;
-    os << "    double kf, dlnkf_dT_fo, dlnkf_dM_fo;\n";
-    os << "    chem_falloff<" << (jac ? "JAC" : "false") << ", " << (r.troe ? "true" : "false") << ", "
+    os << "    " << ty << " kf, dlnkf_dT_fo, dlnkf_dM_fo;\n";
+    os << "    chem_falloff<" << (vjp ? "true" : (jac ? "JAC" : "false")) << ", " << (r.troe ? "true" : "false") << ", "
        << (r.troe && r.troe_has_T2 ? "true" : "false") << ">(lnk, " << num(dlnA) << " + " << num(db) << "*lnT - "
        << num(dth) << "*invT, M, T, invT, " << num(r.k.b) << ", " << num(r.k.theta) << ", " << num(db) << ", "
        << num(dth) << ", " << num(r.troe ? r.troe_alpha : 0.0) << ", " << num(r.troe ? 1.0 / r.troe_T3 : 0.0) << ", "
@@ -103,10 +109,10 @@ static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool ja
   auto nu = m.net(j);
   int dnu = 0;
   for (auto& p : nu) dnu += p.second;
-  os << "    const double Rf = kf*" << conc_product(r.reactants) << ";\n";
+  os << "    const " << ty << " Rf = kf*" << conc_product(r.reactants) << ";\n";
   if (r.reversible) {
     // ln K = -sum nu g/RT + (sum nu) ln(p_ref/(R T))   (eq. equilibrium-constant)
-    os << "    const double lnKc = -(";
+    os << "    const " << ty << " lnKc = -(";
     bool first = true;
     for (auto& p : nu) {
       if (!first) os << " + ";
@@ -120,14 +126,26 @@ static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool ja
     os << ")";
     if (dnu != 0) os << " + " << num(static_cast<double>(dnu)) << "*(LNPREF_R - lnT)";
     os << ";\n";
-    os << "    const double kr = kf*exp(-lnKc);\n";
-    os << "    const double Rr = kr*" << conc_product(r.products) << ";\n";
+    os << "    const " << ty << " kr = kf*exp(-lnKc);\n";
+    os << "    const " << ty << " Rr = kr*" << conc_product(r.products) << ";\n";
   } else {
-    os << "    const double Rr = 0.0;\n";
+    os << "    const " << ty << " Rr = 0.0;\n";
   }
-  os << "    const double q = Rf - Rr;\n";
-  if (!jac) return;  // caller closes the block
+  os << "    const " << ty << " q = Rf - Rr;\n";
+  if (!jac && !vjp) return;  // caller closes the block
+  if (vjp) {
+    os << "    const R sig = ";
+    bool first = true;
+    for (auto& p : nu) {
+      os << (first ? "" : " + ") << num(static_cast<double>(p.second)) << "*ut[" << p.first << "]";
+      first = false;
+    }
+    if (first) os << "0.0";
+    os << ";\n    g[" << J << "] += chem_gpart(q*sig, gmode);\n";
+    for (auto& p : nu) os << "    w[" << p.first << "] += " << num(static_cast<double>(p.second)) << "*q;\n";
+  }
   for (auto& p : nu) {
+    if (vjp) break;
     if (p.second == 1)
       os << "    w[" << p.first << "] += q;\n";
     else if (p.second == -1)
@@ -135,14 +153,14 @@ static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool ja
     else
       os << "    w[" << p.first << "] = fma(" << num(static_cast<double>(p.second)) << ", q, w[" << p.first << "]);\n";
   }
-  os << "    if (JAC) {\n";
+  os << (vjp ? "    {\n" : "    if (JAC) {\n");
   if (r.kind == RxKind::Falloff) {
-    os << "      const double dlnkf_dT = dlnkf_dT_fo;\n";
+    os << "      const " << ty << " dlnkf_dT = dlnkf_dT_fo;\n";
   } else {
-    os << "      const double dlnkf_dT = (" << num(r.k.b) << " + " << num(r.k.theta) << "*invT)*invT;\n";
+    os << "      const " << ty << " dlnkf_dT = (" << num(r.k.b) << " + " << num(r.k.theta) << "*invT)*invT;\n";
   }
   if (r.reversible) {
-    os << "      const double dlnKc_dT = (";
+    os << "      const " << ty << " dlnKc_dT = (";
     bool first = true;
     for (auto& p : nu) {
       if (!first) os << " + ";
@@ -154,9 +172,9 @@ static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool ja
     }
     if (first) os << "0.0";
     os << " - " << num(static_cast<double>(dnu)) << ")*invT;\n";
-    os << "      const double dqdT = q*dlnkf_dT + Rr*dlnKc_dT;\n";
+    os << "      const " << ty << " dqdT = q*dlnkf_dT + Rr*dlnKc_dT;\n";
   } else {
-    os << "      const double dqdT = q*dlnkf_dT;\n";
+    os << "      const " << ty << " dqdT = q*dlnkf_dT;\n";
   }
   // d q / d C_k from mass action on each side
   std::map<int, std::string> dq;
@@ -176,21 +194,28 @@ static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool ja
   }
   if (pd) {
     if (r.kind == RxKind::ThirdBody)
-      os << "      const double qM = q/M;\n";
+      os << "      const " << ty << " qM = q/M;\n";
     else
-      os << "      const double qM = q*dlnkf_dM_fo;\n";
+      os << "      const " << ty << " qM = q*dlnkf_dM_fo;\n";
     for (auto& e : r.eff) {
       std::string t = "qM*" + num(e.second - r.default_eff);
       dq[e.first] = dq.count(e.first) ? dq[e.first] + " + " + t : t;
     }
-    if (r.default_eff != 0.0) {
+    if (vjp && r.default_eff != 0.0) os << "      tbs += " << num(r.default_eff) << "*(sig*qM);\n";
+    if (!vjp && r.default_eff != 0.0) {
       for (auto& p : nu) {
         os << "      tbr[" << p.first << "] = fma(" << num(p.second * r.default_eff) << ", qM, tbr[" << p.first
            << "]);\n";
       }
     }
   }
-  for (auto& d : dq) os << "      const double dq" << d.first << " = " << d.second << ";\n";
+  for (auto& d : dq) os << "      const " << ty << " dq" << d.first << " = " << d.second << ";\n";
+  if (vjp) {
+    os << "      v[0] += sig*dqdT;\n";
+    for (auto& d : dq) os << "      v[" << 1 + d.first << "] += sig*dq" << d.first << ";\n";
+    os << "    }\n";
+    return;
+  }
   for (auto& p : nu) {
     const std::string nv = num(static_cast<double>(p.second));
     auto acc = [&](int colf, const std::string& val) {
@@ -550,6 +575,56 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
     os << ";\n    g[" << j << "] += q * (sm + muT * dH);\n  }\n";
   }
   os << "}\n";
+  // ---- NASA-7 values for a generic value type (plain or dual numbers); the range is chosen by
+  // the value of T
+  os << "template <class R>\n__device__ __forceinline__ void mech_thermo_t(R T, R lnT, R invT, R (&cpR)[NS], R (&hRT)[NS],"
+        " R (&gRT)[NS], R (&dcpR)[NS]) {\n";
+  for (auto& g : groups) {
+    os << "  {\n    const bool hi = chem_val(T) >= " << num(g.first) << ";\n";
+    for (int i : g.second) {
+      const Species& sp = m.species[i];
+      const std::string I = std::to_string(i);
+      auto a = [&](int k) { return std::string("(hi ? ") + num(sp.hi[k]) + " : " + num(sp.lo[k]) + ")"; };
+      os << "    { // " << sp.name << "\n";
+      os << "      cpR[" << I << "] = " << a(0) << " + T*(" << a(1) << " + T*(" << a(2) << " + T*(" << a(3) << " + T*"
+         << a(4) << ")));\n";
+      os << "      hRT[" << I << "] = " << a(0) << " + T*(0.5*" << a(1) << " + T*((1.0/3.0)*" << a(2) << " + T*(0.25*"
+         << a(3) << " + T*(0.2*" << a(4) << ")))) + " << a(5) << "*invT;\n";
+      os << "      gRT[" << I << "] = hRT[" << I << "] - (" << a(0) << "*lnT + T*(" << a(1) << " + T*(0.5*" << a(2)
+         << " + T*((1.0/3.0)*" << a(3) << " + T*(0.25*" << a(4) << ")))) + " << a(6) << ");\n";
+      os << "      dcpR[" << I << "] = " << a(1) << " + T*(2.0*" << a(2) << " + T*(3.0*" << a(3) << " + T*(4.0*" << a(4)
+         << ")));\n    }\n";
+    }
+    os << "  }\n";
+  }
+  os << "}\n";
+  // ---- vector-Jacobian product for the Rosenbrock adjoint, without forming J:
+  //   v = J(y)^T u,  g_j += q_j(y) (u^T dS/dlnA_j(y)) / q_j = q_j sig_j
+  // With ut_s = u_{1+s} - u_0 T hw_s / D (the T row folded into the species weights, omega_T =
+  // -T N / D), (J^T u)_k = sum_j sig_j dq_j/dy_k + [k >= 1] sum_s ut_s tbr_s + u_0 x (the T row's
+  // own terms: -s1/D + A s3 for k = 0, A cw_{k-1} otherwise), sig_j = sum_s nu_sj ut_s.  For
+  // dual-number states y + eps d the dual parts are the directional derivatives along d.
+  os << "template <class R, class GACC>\n"
+        "__device__ CHEM_EVAL_INLINE void mech_vjp(const R (&y)[NY], const double* __restrict__ lnA, int energy,"
+        " const double (&u)[NY], R (&v)[NY], GACC& g, int gmode) {\n";
+  os << "  const R T = y[0];\n  const R lnT = log(T);\n  const R invT = 1.0 / T;\n";
+  os << "  R C[NS];\n#pragma unroll\n  for (int i = 0; i < NS; ++i) C[i] = y[1 + i];\n";
+  os << "  R cpR[NS], hRT[NS], gRT[NS], dcpR[NS];\n  mech_thermo_t(T, lnT, invT, cpR, hRT, gRT, dcpR);\n";
+  if (any_pd) os << "  R Mc = 0.0;\n#pragma unroll\n  for (int i = 0; i < NS; ++i) Mc += C[i];\n";
+  os << "  const double off = energy ? 1.0 : 0.0;\n  R D = 0.0;\n"
+        "#pragma unroll\n  for (int i = 0; i < NS; ++i) D += C[i] * (cpR[i] - off);\n";
+  os << "  const R invD = 1.0 / D;\n  const R uT = -u[0] * T * invD;\n";
+  os << "  R ut[NS], w[NS];\n#pragma unroll\n  for (int i = 0; i < NS; ++i) {\n    ut[i] = u[1 + i] + uT * (hRT[i] - off);\n"
+        "    w[i] = 0.0;\n  }\n";
+  os << "#pragma unroll\n  for (int k = 0; k < NY; ++k) v[k] = 0.0;\n  R tbs = 0.0;\n";
+  for (int j = 0; j < nr; ++j) {
+    emit_rate(os, m, j, false, red, true);
+    os << "  }\n";
+  }
+  os << "  R N = 0.0, s1 = 0.0, s3 = 0.0;\n#pragma unroll\n  for (int i = 0; i < NS; ++i) {\n"
+        "    N += (hRT[i] - off) * w[i];\n    s1 += (cpR[i] - off) * w[i];\n    s3 += C[i] * dcpR[i];\n  }\n";
+  os << "  const R A = T * N * invD * invD;\n  v[0] += u[0] * (A * s3 - s1 * invD);\n";
+  os << "#pragma unroll\n  for (int k = 0; k < NS; ++k) v[1 + k] += tbs + u[0] * (A * (cpR[k] - off));\n}\n";
   os << kKernels;
   return os.str();
 }
