@@ -156,6 +156,9 @@ def main():
         extras["adjoint"] = adjoint_ratio(gm, torch, np, dev, Tape, default_options, CHEM_BE, sample_states,
                                           loss_weights, STATE_CONFIGS)
 
+        extras["adjoint_rosenbrock"] = ros2_adjoint_ratio(gm, torch, np, dev, Tape, default_options, sample_states,
+                                                          loss_weights, cfg)
+
     if not args.skip_large:
         extras["ch4like_53_325"] = large_mechanism_legs(torch, np, dev, args)
 
@@ -189,19 +192,49 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def kernel_code_sha256(hsaco_path, symbol):
+    """SHA-256 of one kernel's machine code in a code object (ELF64: the function symbol's bytes
+    in its section), so that a profile stays attached to exactly the code it measured."""
+    import hashlib
+    import struct
+    with open(hsaco_path, "rb") as f:
+        b = f.read()
+    shoff, = struct.unpack_from("<Q", b, 0x28)
+    shentsize, shnum = struct.unpack_from("<HH", b, 0x3A)
+    secs = [struct.unpack_from("<IIQQQQIIQQ", b, shoff + i * shentsize) for i in range(shnum)]
+    for sec in secs:
+        if sec[1] != 2:           # SHT_SYMTAB
+            continue
+        strtab = secs[sec[6]]
+        for k in range(sec[5] // 24):
+            name_off, info, other, shndx, value, size = struct.unpack_from("<IBBHQQ", b, sec[4] + k * 24)
+            start = strtab[4] + name_off
+            name = b[start:b.index(b"\0", start)].decode()
+            if name == symbol and (info & 0xF) == 2:       # STT_FUNC
+                text = secs[shndx]
+                off = text[4] + (value - text[3])
+                return hashlib.sha256(b[off:off + size]).hexdigest()
+    raise KeyError(symbol)
+
+
 def measured_traffic(mech_path):
     """HBM bytes per split step of the integration kernel from the committed rocprofv3 record
-    (FETCH_SIZE and WRITE_SIZE, calibrated against a copy kernel), or None when the code object
-    in use is not the one that was profiled."""
+    (FETCH_SIZE and WRITE_SIZE, calibrated against a copy kernel), or None when the kernel's
+    machine code differs from the code that was profiled."""
     from paper_2510_10005_amd._binding import precompile
     rec_path = os.path.join(ROOT, "profiles", "ros2_persistent_h2like_1m_traffic.json")
     if not os.path.exists(rec_path):
         return None
     with open(rec_path) as f:
         rec = json.load(f)
-    current = os.path.basename(precompile(mech_path, KERNEL_CACHE))
-    if current != rec["code_object"]:
-        log(f"traffic: profiled code object {rec['code_object']} is not the current {current}; reporting null")
+    if "kernel" not in rec or "kernel_code_sha256" not in rec:
+        log("traffic: the profile record names no kernel code hash; reporting null")
+        return None
+    code = precompile(mech_path, KERNEL_CACHE)
+    digest = kernel_code_sha256(code, rec["kernel"])
+    if digest != rec["kernel_code_sha256"]:
+        log(f"traffic: {rec['kernel']} in {os.path.basename(code)} is not the profiled code "
+            f"({digest[:12]} vs {rec['kernel_code_sha256'][:12]}); reporting null")
         return None
     return rec["bytes_per_step"]
 
@@ -310,6 +343,53 @@ def adjoint_ratio(gm, torch, np, dev, Tape, default_options, CHEM_BE, sample_sta
          "newton_iterations": int(cnt[2].sum().item()), "failed_cells": int((st != 0).sum().item())}
     log(f"adjoint ({mech_name}): forward {t_fwd * 1e3:.1f} ms, with tape {t_fwd_tape * 1e3:.1f} ms, "
         f"adjoint {t_adj * 1e3:.1f} ms, ratio {t_adj / t_fwd:.2f}")
+    return r
+
+
+def ros2_adjoint_ratio(gm, torch, np, dev, Tape, default_options, sample_states, loss_weights, cfg, n=16384,
+                       dt=1e-6, ckpt=50, max_steps=20000):
+    """Rosenbrock forward (adaptive, persistent; with and without the tape) vs its discrete adjoint
+    on the first n cells of the headline state distribution over the same split step."""
+    from paper_2510_10005_amd import CHEM_PERSISTENT, CHEM_ROS2
+    T, p, Y = sample_states(gm.ns, n, cfg.seed, cfg.T_range, cfg.alpha, cfg.p)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    y0 = torch.empty((gm.n, n), dtype=torch.float64, device=dev)
+    gm.chem_state_from_TPY(n, n, t(T), t(p), t(Y.T), y0)
+    y = torch.empty_like(y0)
+    st = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt = torch.zeros((3, n), dtype=torch.int32, device=dev)
+    opts = default_options(method=CHEM_ROS2, dt=dt, n_steps=0, form=CHEM_PERSISTENT)
+    tape = Tape(gm, n, ckpt, method=CHEM_ROS2, max_steps=max_steps)
+    lam = t(np.ascontiguousarray(loss_weights(n, gm.n).T))
+    d0 = torch.empty_like(y0)
+    g = torch.zeros(gm.nr, dtype=torch.float64, device=dev)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - a
+
+    def fwd(tp):
+        y.copy_(y0)
+        gm.chem_integrate(n, n, y, None, opts, tp, st, cnt)
+
+    fwd(tape)
+    gm.chem_integrate_adjoint(tape, None, lam, d0, g)
+    t_fwd = min(timed(lambda: fwd(None)) for _ in range(2))
+    t_fwd_tape = min(timed(lambda: fwd(tape)) for _ in range(2))
+    t_adj = min(timed(lambda: gm.chem_integrate_adjoint(tape, None, lam, d0, g)) for _ in range(2))
+    acc = int(cnt[0].sum().item())
+    r = {"workload": f"{gm.ns}-species mechanism, {n} cells of the headline state set, adaptive Rosenbrock over "
+                     f"{dt:g} s, checkpoints every {ckpt} accepted steps",
+         "forward_ms": t_fwd * 1e3, "forward_with_tape_ms": t_fwd_tape * 1e3, "adjoint_ms": t_adj * 1e3,
+         "adjoint_over_forward": t_adj / t_fwd, "total_over_forward": (t_fwd_tape + t_adj) / t_fwd,
+         "accepted_steps": acc, "max_accepted_per_cell": int(cnt[0].max().item()),
+         "adjoint_steps_per_s": acc / t_adj, "failed_cells": int((st != 0).sum().item())}
+    log(f"Rosenbrock adjoint: forward {t_fwd * 1e3:.1f} ms, with tape {t_fwd_tape * 1e3:.1f} ms, adjoint "
+        f"{t_adj * 1e3:.1f} ms ({acc} accepted steps, max {r['max_accepted_per_cell']} per cell), ratio "
+        f"{t_adj / t_fwd:.2f}, failed cells {r['failed_cells']}")
     return r
 
 
