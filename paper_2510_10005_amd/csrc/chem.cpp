@@ -500,7 +500,6 @@ chem_err chem_source_terms(const chem_mech* M, int64_t n, int64_t ld, const doub
   if (energy != CHEM_CONST_P && energy != CHEM_CONST_V) return fail(CHEM_EINVAL, "unknown energy mode");
   const double* la = lnA ? lnA : M->lnA_default.as<double>();
   void* args[] = {&n, &ld, &y, &la, &energy, &dydt};
-  if (M->wave) return launch(M, K_SOURCE, static_cast<unsigned>(n), 64, static_cast<hipStream_t>(stream), args);
   return launch(M, K_SOURCE, blocks_for(n, 256), 256, static_cast<hipStream_t>(stream), args);
 }
 

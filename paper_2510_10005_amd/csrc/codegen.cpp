@@ -485,6 +485,32 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
   const bool wave = n > dense_limit;
   os << "#define CHEM_WAVE " << (wave ? 1 : 0) << "\n";
   if (wave) {
+    // source terms alone need only C, g/RT and the production rates per cell, few enough values
+    // for one cell per lane with the constants folded into straight-line code (API kernel)
+    os << "__device__ void mech_source_lane(const double (&y)[NY], const double* __restrict__ lnA, int energy,"
+          " double (&S)[NY]) {\n";
+    os << "  const double T = y[0];\n  const double lnT = log(T);\n  const double invT = 1.0 / T;\n";
+    os << "  double C[NS];\n#pragma unroll\n  for (int i = 0; i < NS; ++i) C[i] = y[1 + i];\n";
+    os << "  double gRT[NS];\n  mech_thermo_g(T, lnT, invT, gRT);\n";
+    if (any_pd) os << "  double Mc = 0.0;\n#pragma unroll\n  for (int i = 0; i < NS; ++i) Mc += C[i];\n";
+    os << "  double w[NS];\n#pragma unroll\n  for (int i = 0; i < NS; ++i) w[i] = 0.0;\n";
+    for (int j = 0; j < nr; ++j) {
+      emit_rate(os, m, j, false, red);
+      for (auto& p : m.net(j)) {
+        if (p.second == 1)
+          os << "    w[" << p.first << "] += q;\n";
+        else if (p.second == -1)
+          os << "    w[" << p.first << "] -= q;\n";
+        else
+          os << "    w[" << p.first << "] = fma(" << num(static_cast<double>(p.second)) << ", q, w[" << p.first << "]);\n";
+      }
+      os << "  }\n";
+    }
+    os << "  double hRT[NS], cpR[NS];\n  mech_thermo_hcp(T, invT, hRT, cpR);\n";
+    os << "  const double off = energy ? 1.0 : 0.0;\n  double N = 0.0, D = 0.0;\n";
+    os << "#pragma unroll\n  for (int i = 0; i < NS; ++i) {\n    N = fma(hRT[i] - off, w[i], N);\n"
+          "    D = fma(C[i], cpR[i] - off, D);\n  }\n";
+    os << "  S[0] = -T * N / D;\n#pragma unroll\n  for (int i = 0; i < NS; ++i) S[1 + i] = w[i];\n}\n";
     emit_wave_tables(os, m);
     os << kKernels;
     os << kWave;
