@@ -787,7 +787,9 @@ static chem_err ros2_adjoint(chem_mech* M, chem_tape* tape, const double* la, co
   int64_t total = static_cast<int64_t>(grid) * block;
   chem_err e;
   const int K = tape->opts.ckpt_every;
-  if ((e = M->seg.ensure(sizeof(double) * static_cast<size_t>(K) * NY * total))) return e;
+  // per-step records of one segment: state, LU factors and pivots, two stages (SEG_W values)
+  const size_t seg_w = 4 * static_cast<size_t>(NY) + static_cast<size_t>(NY) * NY;
+  if ((e = M->seg.ensure(sizeof(double) * static_cast<size_t>(K) * seg_w * total))) return e;
   if ((e = M->gpart.ensure(sizeof(double) * static_cast<size_t>(grid) * NR))) return e;
   DevChemOpts o = tape->opts;
   const int* st = tape->status.as<int>();
