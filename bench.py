@@ -394,7 +394,8 @@ def ros2_adjoint_ratio(gm, torch, np, dev, Tape, default_options, sample_states,
 
 
 def large_mechanism_legs(torch, np, dev, args):
-    """The 53-species / 325-reaction mechanism (one wavefront per cell): source-term and Jacobian
+    """The 53-species / 325-reaction mechanism (source terms one cell per lane, Jacobian one wavefront
+    per cell): source-term and Jacobian
     kernels over the 262,144-cell state set.  Its integration is switched off in this version
     (reported as such)."""
     from paper_2510_10005_amd import Mechanism
@@ -410,7 +411,8 @@ def large_mechanism_legs(torch, np, dev, args):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     y0 = torch.empty((gm.n, n), dtype=torch.float64, device=dev)
     gm.chem_state_from_TPY(n, n, t(T), t(p), t(Y.T), y0)
-    out = {"workload": f"ch4like_53_325, {n} cells, T0~U[800,2600] K, Dirichlet(0.5), one wavefront per cell",
+    out = {"workload": f"ch4like_53_325, {n} cells, T0~U[800,2600] K, Dirichlet(0.5); source terms one cell per "
+                       "lane, Jacobian one wavefront per cell",
            "integration": "switched off in this version (GPU run did not complete; cause not identified)"}
     out["api_kernels"] = api_kernel_rates(gm, counts, y0, n, torch, dev, reps=3)
     return out
