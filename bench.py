@@ -394,10 +394,9 @@ def ros2_adjoint_ratio(gm, torch, np, dev, Tape, default_options, sample_states,
 
 
 def large_mechanism_legs(torch, np, dev, args):
-    """The 53-species / 325-reaction mechanism (source terms one cell per lane, Jacobian one wavefront
-    per cell): source-term and Jacobian
-    kernels over the 262,144-cell state set.  Its integration is switched off in this version
-    (reported as such)."""
+    """The 53-species / 325-reaction mechanism: source-term (one cell per lane) and Jacobian (one
+    wavefront per cell) kernels over the 262,144-cell state set.  Its integration is switched off
+    in this version (reported as such)."""
     from paper_2510_10005_amd import Mechanism
     from paper_2510_10005_amd.flops import MechanismCounts
     from synth import mechanism_file
