@@ -6,6 +6,8 @@
   (eqs. Backward_euler, newtons-method-2, jacobian: G = I/dt - J re-evaluated every
   iteration).  A step whose Newton iteration fails is split into two halves, recursively,
   as YASS halves its step (Appendix A.4), down to a maximum depth.
+* ``integrate_sdirk2``: the two-stage SDIRK scheme of Appendix A.1 (gamma = 1 - sqrt(2)/2) at
+  fixed steps, each stage solved by full Newton from the initial guess S(y_n).
 * ``integrate_ros2``: the two-stage Rosenbrock method of Appendix A.3 with
   gamma = 1 + sqrt(2)/2, alpha = 1/gamma, beta = -2/gamma, m1 = 3/(2 gamma),
   m2 = 1/(2 gamma); the second stage right-hand side is S(y + alpha G1) + (beta/h) G1
@@ -206,6 +208,99 @@ def integrate_be(mech, y0, dt_total, n_steps, lnA=None, opt=None, record=False):
     if record:
         out["trajectory"] = traj
     return out
+
+
+# ----------------------------------------------------------------------------- SDIRK-2
+
+SDIRK2_GAMMA = 1.0 - math.sqrt(2.0) / 2.0
+
+
+def _sdirk2_stage(mech, base, h, guess, rho, lnA, opt):
+    """Newton for one SDIRK-2 stage of every cell: Gamma = S(base + gamma h Gamma).
+
+    Iteration k solves (I - gamma h J(Y_k)) delta = -(Gamma_k - S(Y_k)) with
+    Y_k = base + gamma h Gamma_k and sets Gamma_{k+1} = Gamma_k + delta (Appendix A.1, eqs.
+    newtons-method-sdirk2*).  The decrement test reads the state change gamma h delta in the
+    backward-Euler Newton scales (scales from Y_{k+1}); failure as for backward Euler: the scaled
+    norm grows from iteration 2 on, a non-finite or T <= 0 stage state, or ``newton_max``
+    iterations.  Returns (Gamma, converged, iterations).
+    """
+    m, n = base.shape
+    gh = SDIRK2_GAMMA * h
+    gam = guess.copy()
+    active = np.ones(m, dtype=bool)
+    conv = np.zeros(m, dtype=bool)
+    iters = np.zeros(m, dtype=np.int32)
+    prev = np.full(m, np.inf)
+    eye = np.eye(n)
+    for k in range(opt.newton_max):
+        idx = np.nonzero(active)[0]
+        if idx.size == 0:
+            break
+        Yk = base[idx] + gh * gam[idx]
+        f = gam[idx] - source_terms(mech, Yk, lnA, opt.energy)
+        G = eye[None] - gh * jacobian(mech, Yk, lnA, opt.energy)
+        with np.errstate(all="ignore"):
+            delta = np.full_like(Yk, np.nan)
+            for c in range(idx.size):
+                try:
+                    delta[c] = np.linalg.solve(G[c], -f[c])
+                except np.linalg.LinAlgError:
+                    pass
+            gnew = gam[idx] + delta
+            Ynew = base[idx] + gh * gnew
+            norm = np.max(np.abs(gh * delta) / _newton_scale(mech, Ynew, rho[idx], opt), axis=1)
+        iters[idx] += 1
+        bad = ~np.all(np.isfinite(Ynew), axis=1) | ~(Ynew[:, 0] > 0.0) | ~np.isfinite(norm)
+        diverged = (k >= 2) & (norm > prev[idx])
+        done = ~bad & (norm <= 1.0)
+        gam[idx] = np.where(bad[:, None], gam[idx], gnew)
+        conv[idx[done]] = True
+        stop = bad | done | diverged
+        active[idx[stop]] = False
+        prev[idx] = norm
+    return gam, conv, iters
+
+
+def sdirk2_step(mech, y, h, lnA, opt):
+    """One SDIRK-2 step (Appendix A.1) of size h for every cell of y ([m, n]):
+
+        Gamma1 = S(y + gamma h Gamma1),  Gamma2 = S(y + (1 - gamma) h Gamma1 + gamma h Gamma2),
+        y' = y + h ((1 - gamma) Gamma1 + gamma Gamma2),  gamma = 1 - sqrt(2)/2,
+
+    each stage solved by Newton from the initial guess S(y).  Returns (y', converged, iterations).
+    """
+    rho = (y[:, 1:] * mech.W[None, :]).sum(axis=1)
+    S0 = source_terms(mech, y, lnA, opt.energy)
+    g1, c1, i1 = _sdirk2_stage(mech, y, h, S0, rho, lnA, opt)
+    base2 = y + (1.0 - SDIRK2_GAMMA) * h * g1
+    g2, c2, i2 = _sdirk2_stage(mech, base2, h, S0, rho, lnA, opt)
+    ynew = y + h * ((1.0 - SDIRK2_GAMMA) * g1 + SDIRK2_GAMMA * g2)
+    ok = c1 & c2 & np.all(np.isfinite(ynew), axis=1) & (ynew[:, 0] > 0.0)
+    return ynew, ok, i1 + np.where(c1, i2, 0)
+
+
+def integrate_sdirk2(mech, y0, dt_total, n_steps, lnA=None, opt=None):
+    """SDIRK-2 over ``n_steps`` fixed steps of dt_total/n_steps for every cell (the paper's use,
+    Table 5).  A cell whose step fails keeps its last state and gets CELL_NEWTON_FAIL (the paper
+    names no fallback for the SDIRK schemes).  Returns dict(y, status, steps, newton)."""
+    opt = opt or IntegratorOptions()
+    y = np.array(y0, dtype=float, copy=True)
+    nc = y.shape[0]
+    status = _input_status(y)
+    steps = np.zeros(nc, dtype=np.int32)
+    newton = np.zeros(nc, dtype=np.int64)
+    h = dt_total / n_steps
+    for _ in range(n_steps):
+        idx = np.nonzero(status == CELL_OK)[0]
+        if idx.size == 0:
+            break
+        ynew, ok, it = sdirk2_step(mech, y[idx], h, lnA, opt)
+        newton[idx] += it
+        y[idx[ok]] = ynew[ok]
+        steps[idx[ok]] += 1
+        status[idx[~ok]] = CELL_NEWTON_FAIL
+    return dict(y=y, status=status, steps=steps, newton=newton)
 
 
 # ----------------------------------------------------------------------------- Rosenbrock
