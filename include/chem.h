@@ -61,7 +61,7 @@ enum {
   CHEM_CELL_T_RANGE = 5        /* input temperature <= 0 */
 };
 
-enum { CHEM_BE = 0, CHEM_ROS2 = 1 };
+enum { CHEM_BE = 0, CHEM_ROS2 = 1, CHEM_SDIRK2 = 2 };
 enum { CHEM_CONST_P = 0, CHEM_CONST_V = 1 };
 enum { CHEM_PERSISTENT = 0, CHEM_PLAIN = 1 };
 enum { CHEM_FLAG_CHECK_CELLS = 1 };  /* synchronise and return CHEM_ECELLS if a cell failed */
@@ -75,6 +75,12 @@ enum { CHEM_FLAG_CHECK_CELLS = 1 };  /* synchronise and return CHEM_ECELLS if a 
  *           CHEM_ROS2: two-stage Rosenbrock of Appendix A.3 from t = 0 to dt; adaptive step size
  *                    (embedded first-order solution, weighted RMS error, rtol/atol on T [K] and
  *                    on mass fractions) unless n_steps > 0, which gives fixed steps dt/n_steps.
+ *           CHEM_SDIRK2: two-stage SDIRK of Appendix A.1 (gamma = 1 - sqrt(2)/2), n_steps fixed steps
+ *                    of dt/n_steps (0 means 1); each stage Gamma = S(b + gamma h Gamma) is solved by
+ *                    full Newton, (I - gamma h J) delta = -(Gamma - S), from the guess S(y_n), with
+ *                    the state change gamma h delta in the Newton test below.  A failed step sets
+ *                    CHEM_CELL_NEWTON_FAIL (no halving).  Persistent form only, n <= 24 only, no
+ *                    adjoint tape; counters: completed steps, 0, Newton iterations.
  *  energy   CHEM_CONST_P: omega_T = -sum H_i omega_i / sum C_i Cp_i (Appendix B)
  *           CHEM_CONST_V: omega_T = -sum U_i omega_i / sum C_i Cv_i (Section 3)
  *  form     CHEM_PERSISTENT: one persistent kernel, cells pulled from a work queue lane by lane.

@@ -55,14 +55,19 @@ const char* kKernelNames[] = {
     "chem_k_ros2_persistent", "chem_k_ros2_init",       "chem_k_ros2_step",        "chem_k_be_persistent",
     "chem_k_be_init",       "chem_k_be_step",          "chem_k_be_adjoint",       "chem_k_reduce_blocks",
     "chem_k_sched_scan",    "chem_k_sched_scatter",    "chem_k_jac_transpose",    "chem_k_ros2_persistent_rec",
-    "chem_k_ros2_adjoint"};
+    "chem_k_ros2_adjoint",  "chem_k_sdirk2_persistent"};
 enum KernelId {
   K_THERMO, K_SOURCE, K_JACOBIAN, K_TPY, K_MASSFRAC, K_TPY_VJP, K_MASSFRAC_VJP, K_FILL_U64,
   K_ROS2_PERSISTENT, K_ROS2_INIT, K_ROS2_STEP, K_BE_PERSISTENT, K_BE_INIT, K_BE_STEP, K_BE_ADJOINT,
-  K_REDUCE_BLOCKS, K_SCHED_SCAN, K_SCHED_SCATTER, K_JAC_TRANSPOSE, K_ROS2_PERSISTENT_REC, K_ROS2_ADJOINT, K_COUNT
+  K_REDUCE_BLOCKS, K_SCHED_SCAN, K_SCHED_SCATTER, K_JAC_TRANSPOSE, K_ROS2_PERSISTENT_REC, K_ROS2_ADJOINT,
+  K_SDIRK2_PERSISTENT, K_COUNT
 };
 // kernels that only the register-resident form (n <= kDenseLimit) has
-bool dense_only(int k) { return k == K_ROS2_PERSISTENT_REC || k == K_ROS2_ADJOINT; }
+bool dense_only(int k) { return k == K_ROS2_PERSISTENT_REC || k == K_ROS2_ADJOINT || k == K_SDIRK2_PERSISTENT; }
+// persistent integration kernel of a method
+KernelId persistent_kernel(int method) {
+  return method == CHEM_ROS2 ? K_ROS2_PERSISTENT : (method == CHEM_SDIRK2 ? K_SDIRK2_PERSISTENT : K_BE_PERSISTENT);
+}
 constexpr int kSchedBins = 256;  // CHEM_SCHED_BINS in the device code
 
 struct DevChemOpts {  // layout mirrors ChemOpts in the generated source
@@ -120,7 +125,7 @@ std::vector<std::string> compile_options(const std::string& arch) {
 // a larger one is split into one program per group, compiled concurrently, because its code is
 // large enough that a single compile is slow.
 constexpr int kGroups = 4;
-const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1, 0, 1, 3};
+const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1, 0, 1, 3, 2};
 
 struct CodeObject {
   std::string code, path;
@@ -257,8 +262,8 @@ struct chem_mech {
   bool wave = false;  // one cell per 64-lane wavefront (blocks of 64)
   DevBuf lnA_default, queue, ws, wst, counters_internal, running, seg, gws, gpart, sched, order, jstage;
   unsigned int* running_host = nullptr;
-  int launch_block[2][2] = {{0, 0}, {0, 0}};  // [method][form]
-  int launch_grid[2][2] = {{0, 0}, {0, 0}};
+  int launch_block[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // [method][form]
+  int launch_grid[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   std::mutex mu;
   ~chem_mech() {
     if (running_host) (void)hipHostFree(running_host);
@@ -310,7 +315,7 @@ DevChemOpts to_dev(const chem_integrator_opts& o, int ckpt_every) {
   d.newton_rtol = o.newton_rtol;
   d.newton_atol_T = o.newton_atol_T;
   d.newton_atol_Y = o.newton_atol_Y;
-  d.n_steps = (o.method == CHEM_BE && o.n_steps < 1) ? 1 : o.n_steps;
+  d.n_steps = (o.method != CHEM_ROS2 && o.n_steps < 1) ? 1 : o.n_steps;
   d.max_steps = o.max_steps;
   d.newton_max = o.newton_max;
   d.halving_max_depth = o.halving_max_depth;
@@ -321,7 +326,8 @@ DevChemOpts to_dev(const chem_integrator_opts& o, int ckpt_every) {
 
 chem_err validate_opts(const chem_integrator_opts* o) {
   if (!o) return fail(CHEM_EINVAL, "null options");
-  if (o->method != CHEM_BE && o->method != CHEM_ROS2) return fail(CHEM_EINVAL, "unknown method");
+  if (o->method != CHEM_BE && o->method != CHEM_ROS2 && o->method != CHEM_SDIRK2)
+    return fail(CHEM_EINVAL, "unknown method");
   if (o->energy != CHEM_CONST_P && o->energy != CHEM_CONST_V) return fail(CHEM_EINVAL, "unknown energy mode");
   if (o->form != CHEM_PERSISTENT && o->form != CHEM_PLAIN) return fail(CHEM_EINVAL, "unknown form");
   if (!(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(CHEM_EINVAL, "dt must be positive and finite");
@@ -611,6 +617,10 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
   if (chem_err e = check_cells(M, n, ld)) return e;
   if (chem_err e = validate_opts(opts)) return e;
   if (M->wave) return fail(CHEM_EUNSUPPORTED, kWaveIntegrationOff);
+  if (opts->method == CHEM_SDIRK2) {
+    if (opts->form != CHEM_PERSISTENT) return fail(CHEM_EUNSUPPORTED, "SDIRK-2 runs in the persistent form");
+    if (tape) return fail(CHEM_EUNSUPPORTED, "no adjoint tape for SDIRK-2");
+  }
   if (tape) {
     if (tape->mech != M) return fail(CHEM_EINVAL, "tape belongs to another mechanism");
     if (tape->method != opts->method) return fail(CHEM_EINVAL, "tape was created for another method");
@@ -666,7 +676,7 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
   }
   const int method = opts->method;
   if (opts->form == CHEM_PERSISTENT) {
-    const KernelId k = method == CHEM_ROS2 ? (hs ? K_ROS2_PERSISTENT_REC : K_ROS2_PERSISTENT) : K_BE_PERSISTENT;
+    const KernelId k = (method == CHEM_ROS2 && hs) ? K_ROS2_PERSISTENT_REC : persistent_kernel(method);
     int block;
     unsigned grid;
     persistent_config(M, method, k, block, grid);
@@ -678,7 +688,10 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
     }
     uint64_t* q = M->queue.as<uint64_t>();
     if ((e = fill_u64(M, q, 1, 0, s))) return e;
-    if (method == CHEM_ROS2) {
+    if (method == CHEM_SDIRK2) {
+      void* args[] = {&n, &ld, &y, &la, &o, &status, &cnt, &q};
+      if ((e = launch(M, k, grid, block, s, args))) return e;
+    } else if (method == CHEM_ROS2) {
       const unsigned shm = shmem_for(M, k, block);
       int budget = opts->probe_attempts;
       if (n >= (int64_t(1) << 31)) budget = 0;
@@ -855,7 +868,8 @@ chem_err chem_integrate_adjoint(const chem_mech* Mc, chem_tape* tape, const doub
 
 chem_err chem_set_launch(chem_mech* M, int method, int form, int block, int grid) {
   if (!M) return fail(CHEM_EINVAL, "null mechanism");
-  if ((method != CHEM_BE && method != CHEM_ROS2) || (form != CHEM_PERSISTENT && form != CHEM_PLAIN))
+  if ((method != CHEM_BE && method != CHEM_ROS2 && method != CHEM_SDIRK2) ||
+      (form != CHEM_PERSISTENT && form != CHEM_PLAIN))
     return fail(CHEM_EINVAL, "unknown method or form");
   if (block != 0 && (block < 64 || block > kMaxBlock || block % 64)) return fail(CHEM_EINVAL, "block must be 64..256, a multiple of 64");
   if (grid < 0) return fail(CHEM_EINVAL, "grid must be >= 0");
@@ -866,12 +880,13 @@ chem_err chem_set_launch(chem_mech* M, int method, int form, int block, int grid
 
 chem_err chem_get_launch(const chem_mech* M, int method, int form, int* block, int* grid) {
   if (!M || !block || !grid) return fail(CHEM_EINVAL, "null argument");
-  if ((method != CHEM_BE && method != CHEM_ROS2) || (form != CHEM_PERSISTENT && form != CHEM_PLAIN))
+  if ((method != CHEM_BE && method != CHEM_ROS2 && method != CHEM_SDIRK2) ||
+      (form != CHEM_PERSISTENT && form != CHEM_PLAIN))
     return fail(CHEM_EINVAL, "unknown method or form");
   if (form == CHEM_PERSISTENT) {
     int b;
     unsigned g;
-    persistent_config(M, method, method == CHEM_ROS2 ? K_ROS2_PERSISTENT : K_BE_PERSISTENT, b, g);
+    persistent_config(M, method, persistent_kernel(method), b, g);
     *block = b;
     *grid = static_cast<int>(g);
   } else {
@@ -898,7 +913,7 @@ chem_err chem_autotune(chem_mech* M, int64_t n, int64_t ld, const double* y, con
   hipEvent_t a, b;
   HIP_TRY(hipEventCreate(&a));
   HIP_TRY(hipEventCreate(&b));
-  const KernelId k = opts->method == CHEM_ROS2 ? K_ROS2_PERSISTENT : K_BE_PERSISTENT;
+  const KernelId k = persistent_kernel(opts->method);
   float best = 1e30f;
   int best_block = 64, best_grid = 0;
   const int method = opts->method;

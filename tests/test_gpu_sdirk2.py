@@ -1,0 +1,125 @@
+"""GPU: SDIRK-2 (Appendix A.1, persistent form) against the oracle, cell by cell.
+
+Statuses and completed steps must equal the oracle's, states within 1e-8 (relative, species as
+mass fractions).  Newton iteration counts must agree within one iteration, and exactly for at
+least 97 % of the cells: the convergence test max |gamma h delta| / sc <= 1 can flip between two
+correct answers when the norm lands within rounding of 1 (the LU's rounding order differs).
+Cases: the backward-Euler workload's states at the paper's SDIRK-2 step (7e-7 s) and at
+4 x 5e-7 s, the Rosenbrock workload's states at 5 x 2e-8 s, both energy modes, Newton failure (newton_max = 1), argument errors, the autotuned launch, and
+sampled cells of the 1024-cell workload over its 2e-5 s at the paper's step size.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.integrate import IntegratorOptions
+from synth.states import STATE_CONFIGS, sample_config, sample_states
+
+from _gpu import dev_soa, gpu_mechanism, host_aos, integrated_state_error
+
+pytestmark = pytest.mark.gpu
+
+MECHS = ["tiny_5_6", "tiny_8_14", "h2like_10_27"]
+
+
+@pytest.fixture(scope="module", params=MECHS)
+def mechs(request):
+    print(f"[gpu] loading {request.param}", flush=True)
+    return gpu_mechanism(request.param)
+
+
+def _run(gm, om, y0, dt, n_steps, ld=None, **kw):
+    from paper_2510_10005_amd import CHEM_PERSISTENT, CHEM_SDIRK2, default_options
+    nc = y0.shape[0]
+    ld = ld or nc + 3
+    y = dev_soa(y0, ld)
+    st = torch.full((ld,), -7, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros((3, ld), dtype=torch.int32, device="cuda")
+    opts = default_options(method=CHEM_SDIRK2, dt=dt, n_steps=n_steps, form=CHEM_PERSISTENT, **kw)
+    gm.chem_integrate(nc, ld, y, None, opts, None, st, cnt)
+    torch.cuda.synchronize()
+    return host_aos(y, nc), st.cpu().numpy()[:nc], cnt.cpu().numpy()[:, :nc]
+
+
+def _check_newton(got, ref):
+    d = np.abs(got.astype(np.int64) - ref.astype(np.int64))
+    assert d.max() <= 1 and (d == 0).mean() >= 0.97, (got, ref)
+
+
+CASES = {
+    # name: (state config, cells, dt, n_steps, energy)
+    "paper_step": ("be_small", 150, 7e-7, 1, 0),
+    "four_steps": ("be_small", 150, 2e-6, 4, 0),
+    "four_steps_cv": ("be_small", 150, 2e-6, 4, 1),
+    "hot_states": ("ros2_1m", 150, 1e-7, 5, 0),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_sdirk2_matches_oracle(mechs, case):
+    gm, om = mechs
+    cfg, nc, dt, n_steps, energy = CASES[case]
+    T, p, Y = sample_config(cfg, om.ns, nc)
+    y0 = oracle.state_from_TPY(om, T, p, Y)
+    ref = oracle.integrate_sdirk2(om, y0, dt, n_steps, opt=IntegratorOptions(energy=energy))
+    print(f"[gpu] {om.ns} species, SDIRK-2 {case}", flush=True)
+    got, st, cnt = _run(gm, om, y0, dt, n_steps, energy=energy)
+    np.testing.assert_array_equal(st, ref["status"])
+    np.testing.assert_array_equal(cnt[0], ref["steps"])
+    _check_newton(cnt[2], ref["newton"])
+    ok = ref["status"] == 0
+    err = integrated_state_error(om, got[ok], ref["y"][ok])
+    print(f"[gpu] SDIRK-2 {case}: {ok.sum()} cells, max rel err {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-8
+
+
+def test_sdirk2_newton_failure(mechs):
+    gm, om = mechs
+    T, p, Y = sample_config("be_small", om.ns, 20)
+    y0 = oracle.state_from_TPY(om, T, p, Y)
+    ref = oracle.integrate_sdirk2(om, y0, 1e-6, 2, opt=IntegratorOptions(newton_max=1))
+    got, st, cnt = _run(gm, om, y0, 1e-6, 2, newton_max=1)
+    np.testing.assert_array_equal(st, ref["status"])
+    np.testing.assert_array_equal(cnt[0], ref["steps"])
+    assert np.array_equal(got, y0)
+
+
+def test_sdirk2_argument_errors(mechs):
+    from paper_2510_10005_amd import CHEM_PLAIN, CHEM_SDIRK2, Tape, default_options
+    from paper_2510_10005_amd._binding import ChemError
+    gm, om = mechs
+    y = torch.ones((om.n, 8), dtype=torch.float64, device="cuda")
+    st = torch.zeros(8, dtype=torch.int32, device="cuda")
+    with pytest.raises(ChemError, match="persistent form"):
+        gm.chem_integrate(8, 8, y, None, default_options(method=CHEM_SDIRK2, dt=1e-8, form=CHEM_PLAIN), None, st, None)
+    with pytest.raises(ChemError, match="no adjoint tape"):
+        gm.chem_integrate(8, 8, y, None, default_options(method=CHEM_SDIRK2, dt=1e-8), Tape(gm, 8, 2), st, None)
+
+
+def test_sdirk2_fullsize_sampled_cells_autotuned():
+    """The 1024-cell workload over its 2e-5 s at the paper's SDIRK-2 step (29 steps of 6.9e-7 s),
+    autotuned persistent launch; 32 seeded cells against the oracle."""
+    from paper_2510_10005_amd import CHEM_PERSISTENT, CHEM_SDIRK2, default_options
+    gm, om = gpu_mechanism("h2like_10_27")
+    cfg = STATE_CONFIGS["be_small"]
+    n = cfg.n_cells
+    T, p, Y = sample_states(om.ns, n, cfg.seed, cfg.T_range, cfg.alpha, cfg.p)
+    y0 = oracle.state_from_TPY(om, T, p, Y)
+    opts = default_options(method=CHEM_SDIRK2, dt=2e-5, n_steps=29, form=CHEM_PERSISTENT)
+    yd = dev_soa(y0, n)
+    gm.chem_autotune(n, n, yd, None, opts)
+    print(f"[gpu] SDIRK-2 autotuned launch {gm.chem_get_launch(CHEM_SDIRK2, CHEM_PERSISTENT)}", flush=True)
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros((3, n), dtype=torch.int32, device="cuda")
+    gm.chem_integrate(n, n, yd, None, opts, None, st, cnt)
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(5004).choice(n, size=32, replace=False)
+    ref = oracle.integrate_sdirk2(om, y0[idx], 2e-5, 29)
+    got = yd[:, idx].cpu().numpy().T
+    np.testing.assert_array_equal(st.cpu().numpy()[idx], ref["status"])
+    _check_newton(cnt[2].cpu().numpy()[idx], ref["newton"])
+    err = integrated_state_error(om, got, ref["y"])
+    print(f"[gpu] full-size SDIRK-2: max rel err {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-8
