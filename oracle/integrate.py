@@ -6,8 +6,9 @@
   (eqs. Backward_euler, newtons-method-2, jacobian: G = I/dt - J re-evaluated every
   iteration).  A step whose Newton iteration fails is split into two halves, recursively,
   as YASS halves its step (Appendix A.4), down to a maximum depth.
-* ``integrate_sdirk2``: the two-stage SDIRK scheme of Appendix A.1 (gamma = 1 - sqrt(2)/2) at
-  fixed steps, each stage solved by full Newton from the initial guess S(y_n).
+* ``integrate_sdirk2`` / ``integrate_sdirk4``: the two-stage SDIRK scheme of Appendix A.1
+  (gamma = 1 - sqrt(2)/2) and the five-stage one of Appendix A.2 at fixed steps, each stage
+  solved by full Newton from the initial guess S(y_n).
 * ``integrate_ros2``: the two-stage Rosenbrock method of Appendix A.3 with
   gamma = 1 + sqrt(2)/2, alpha = 1/gamma, beta = -2/gamma, m1 = 3/(2 gamma),
   m2 = 1/(2 gamma); the second stage right-hand side is S(y + alpha G1) + (beta/h) G1
@@ -215,8 +216,8 @@ def integrate_be(mech, y0, dt_total, n_steps, lnA=None, opt=None, record=False):
 SDIRK2_GAMMA = 1.0 - math.sqrt(2.0) / 2.0
 
 
-def _sdirk2_stage(mech, base, h, guess, rho, lnA, opt):
-    """Newton for one SDIRK-2 stage of every cell: Gamma = S(base + gamma h Gamma).
+def _sdirk_stage(mech, base, gh, guess, rho, lnA, opt):
+    """Newton for one SDIRK stage of every cell: Gamma = S(base + gh Gamma), gh = a_pp h.
 
     Iteration k solves (I - gamma h J(Y_k)) delta = -(Gamma_k - S(Y_k)) with
     Y_k = base + gamma h Gamma_k and sets Gamma_{k+1} = Gamma_k + delta (Appendix A.1, eqs.
@@ -226,7 +227,6 @@ def _sdirk2_stage(mech, base, h, guess, rho, lnA, opt):
     iterations.  Returns (Gamma, converged, iterations).
     """
     m, n = base.shape
-    gh = SDIRK2_GAMMA * h
     gam = guess.copy()
     active = np.ones(m, dtype=bool)
     conv = np.zeros(m, dtype=bool)
@@ -262,6 +262,50 @@ def _sdirk2_stage(mech, base, h, guess, rho, lnA, opt):
     return gam, conv, iters
 
 
+# Butcher tableaus (A lower triangular with a constant diagonal, weights b).  SDIRK-2: Appendix
+# A.1.  SDIRK-4: the five-stage tableau printed in Appendix A.2 (7 significant digits), whose
+# a_52 is not printed; it is read as a_52 = b_2, which with a_51 = b_1, a_53 = b_3, a_54 = b_4 and
+# a_55 = b_5 as printed makes the scheme stiffly accurate (last row of A = b).
+SDIRK2_A = np.array([[SDIRK2_GAMMA, 0.0], [1.0 - SDIRK2_GAMMA, SDIRK2_GAMMA]])
+SDIRK2_B = np.array([1.0 - SDIRK2_GAMMA, SDIRK2_GAMMA])
+_G4 = 4.0 / 15.0
+SDIRK4_B = np.array([2.100115, -7.677800e-1, 2.399816, -2.998818, _G4])
+SDIRK4_A = np.array([
+    [_G4, 0.0, 0.0, 0.0, 0.0],
+    [0.5, _G4, 0.0, 0.0, 0.0],
+    [3.541539e-1, -5.415395e-2, _G4, 0.0, 0.0],
+    [8.515494e-2, -6.484332e-2, 7.915325e-2, _G4, 0.0],
+    [2.100115, -7.677800e-1, 2.399816, -2.998818, _G4],
+])
+
+
+def sdirk_step(mech, y, h, A, b, lnA, opt):
+    """One step of the SDIRK scheme (A, b) of size h for every cell of y ([m, n]):
+
+        Gamma_p = S(y + h sum_{j<p} a_pj Gamma_j + a_pp h Gamma_p),  y' = y + h sum_p b_p Gamma_p,
+
+    each stage solved by Newton from the initial guess S(y) (Appendix A.1/A.2).  A cell whose
+    stage fails skips the later stages.  Returns (y', converged, iterations)."""
+    rho = (y[:, 1:] * mech.W[None, :]).sum(axis=1)
+    S0 = source_terms(mech, y, lnA, opt.energy)
+    gams = []
+    ok = np.ones(y.shape[0], dtype=bool)
+    iters = np.zeros(y.shape[0], dtype=np.int32)
+    for p in range(len(b)):
+        base = y.copy()
+        for j in range(p):
+            base = base + (h * A[p, j]) * gams[j]
+        gp, cp, ip = _sdirk_stage(mech, base, h * A[p, p], S0, rho, lnA, opt)
+        iters += np.where(ok, ip, 0)
+        ok &= cp
+        gams.append(gp)
+    ynew = y.copy()
+    for p in range(len(b)):
+        ynew = ynew + (h * b[p]) * gams[p]
+    ok &= np.all(np.isfinite(ynew), axis=1) & (ynew[:, 0] > 0.0)
+    return ynew, ok, iters
+
+
 def sdirk2_step(mech, y, h, lnA, opt):
     """One SDIRK-2 step (Appendix A.1) of size h for every cell of y ([m, n]):
 
@@ -270,20 +314,14 @@ def sdirk2_step(mech, y, h, lnA, opt):
 
     each stage solved by Newton from the initial guess S(y).  Returns (y', converged, iterations).
     """
-    rho = (y[:, 1:] * mech.W[None, :]).sum(axis=1)
-    S0 = source_terms(mech, y, lnA, opt.energy)
-    g1, c1, i1 = _sdirk2_stage(mech, y, h, S0, rho, lnA, opt)
-    base2 = y + (1.0 - SDIRK2_GAMMA) * h * g1
-    g2, c2, i2 = _sdirk2_stage(mech, base2, h, S0, rho, lnA, opt)
-    ynew = y + h * ((1.0 - SDIRK2_GAMMA) * g1 + SDIRK2_GAMMA * g2)
-    ok = c1 & c2 & np.all(np.isfinite(ynew), axis=1) & (ynew[:, 0] > 0.0)
-    return ynew, ok, i1 + np.where(c1, i2, 0)
+    return sdirk_step(mech, y, h, SDIRK2_A, SDIRK2_B, lnA, opt)
 
 
-def integrate_sdirk2(mech, y0, dt_total, n_steps, lnA=None, opt=None):
-    """SDIRK-2 over ``n_steps`` fixed steps of dt_total/n_steps for every cell (the paper's use,
-    Table 5).  A cell whose step fails keeps its last state and gets CELL_NEWTON_FAIL (the paper
-    names no fallback for the SDIRK schemes).  Returns dict(y, status, steps, newton)."""
+def integrate_sdirk(mech, y0, dt_total, n_steps, A, b, lnA=None, opt=None):
+    """An SDIRK scheme (A, b) over ``n_steps`` fixed steps of dt_total/n_steps for every cell (the
+    paper's use, Table 5).  A cell whose step fails keeps its last state and gets
+    CELL_NEWTON_FAIL (the paper names no fallback for the SDIRK schemes).  Returns dict(y, status,
+    steps, newton)."""
     opt = opt or IntegratorOptions()
     y = np.array(y0, dtype=float, copy=True)
     nc = y.shape[0]
@@ -295,12 +333,22 @@ def integrate_sdirk2(mech, y0, dt_total, n_steps, lnA=None, opt=None):
         idx = np.nonzero(status == CELL_OK)[0]
         if idx.size == 0:
             break
-        ynew, ok, it = sdirk2_step(mech, y[idx], h, lnA, opt)
+        ynew, ok, it = sdirk_step(mech, y[idx], h, A, b, lnA, opt)
         newton[idx] += it
         y[idx[ok]] = ynew[ok]
         steps[idx[ok]] += 1
         status[idx[~ok]] = CELL_NEWTON_FAIL
     return dict(y=y, status=status, steps=steps, newton=newton)
+
+
+def integrate_sdirk2(mech, y0, dt_total, n_steps, lnA=None, opt=None):
+    """SDIRK-2 (Appendix A.1) at fixed steps; see ``integrate_sdirk``."""
+    return integrate_sdirk(mech, y0, dt_total, n_steps, SDIRK2_A, SDIRK2_B, lnA, opt)
+
+
+def integrate_sdirk4(mech, y0, dt_total, n_steps, lnA=None, opt=None):
+    """SDIRK-4 (Appendix A.2, five stages) at fixed steps; see ``integrate_sdirk``."""
+    return integrate_sdirk(mech, y0, dt_total, n_steps, SDIRK4_A, SDIRK4_B, lnA, opt)
 
 
 # ----------------------------------------------------------------------------- Rosenbrock
