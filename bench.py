@@ -59,7 +59,8 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2510_10005_amd import (CHEM_BE, CHEM_PERSISTENT, CHEM_PLAIN, CHEM_ROS2, Mechanism, Tape,
+    from paper_2510_10005_amd import (CHEM_BE, CHEM_PERSISTENT, CHEM_PLAIN, CHEM_ROS2, CHEM_SDIRK2, CHEM_SDIRK4,
+                                      Mechanism, Tape,
                                       default_options)
     from paper_2510_10005_amd.flops import MechanismCounts
     from synth import mechanism_file
@@ -151,8 +152,9 @@ def main():
         log(f"plain: {acc_p / wp:.3e} cell-substeps/s ({wp * 1e3:.1f} ms); persistent speedup {value / (acc_p / wp):.2f}x")
 
     extras["be_1024"] = be_small_rate(gm, torch, np, dev, default_options, CHEM_BE, sample_states, STATE_CONFIGS)
-    extras["sdirk2_1024"] = sdirk2_small_rate(gm, counts, torch, np, dev, default_options, sample_states,
-                                              STATE_CONFIGS)
+    for name, method in (("sdirk2_1024", CHEM_SDIRK2), ("sdirk4_1024", CHEM_SDIRK4)):
+        extras[name] = sdirk_small_rate(gm, counts, method, torch, np, dev, default_options, sample_states,
+                                        STATE_CONFIGS)
 
     if not args.skip_adjoint:
         extras["adjoint"] = adjoint_ratio(gm, torch, np, dev, Tape, default_options, CHEM_BE, sample_states,
@@ -274,11 +276,13 @@ def api_kernel_rates(gm, counts, y0, n, torch, dev, reps=5):
     return out
 
 
-def sdirk2_small_rate(gm, counts, torch, np, dev, default_options, sample_states, STATE_CONFIGS):
-    """SDIRK-2 (Appendix A.1) on the 1,024-cell workload's states over its 2e-5 s in 100 steps of
-    2e-7 s, persistent form, autotuned launch.  (At the paper's SDIRK-2 step of 7e-7 s, Table 5,
-    Newton fails in about 15 % of the cells of this synthetic mechanism; SDIRK-2 has no halving.)"""
+def sdirk_small_rate(gm, counts, method, torch, np, dev, default_options, sample_states, STATE_CONFIGS):
+    """SDIRK-2 (Appendix A.1) or SDIRK-4 (Appendix A.2) on the 1,024-cell workload's states over its
+    2e-5 s in 100 steps of 2e-7 s, persistent form, autotuned launch.  (At the paper's steps, 7e-7 s
+    and 1e-6 s, Table 5, Newton fails in about 15 % and 20 % of the cells of this synthetic
+    mechanism; the SDIRK schemes have no halving.)"""
     from paper_2510_10005_amd import CHEM_PERSISTENT, CHEM_SDIRK2
+    label, stages = ("SDIRK-2", 2) if method == CHEM_SDIRK2 else ("SDIRK-4", 5)
     cfg = STATE_CONFIGS["be_small"]
     n = cfg.n_cells
     T, p, Y = sample_states(gm.ns, n, cfg.seed, cfg.T_range, cfg.alpha, cfg.p)
@@ -288,7 +292,7 @@ def sdirk2_small_rate(gm, counts, torch, np, dev, default_options, sample_states
     y = torch.empty_like(y0)
     st = torch.empty(n, dtype=torch.int32, device=dev)
     cnt = torch.zeros((3, n), dtype=torch.int32, device=dev)
-    opts = default_options(method=CHEM_SDIRK2, dt=2e-5, n_steps=100, form=CHEM_PERSISTENT)
+    opts = default_options(method=method, dt=2e-5, n_steps=100, form=CHEM_PERSISTENT)
     gm.chem_autotune(n, n, y0, None, opts)
     best = 1e30
     for _ in range(3):
@@ -300,14 +304,17 @@ def sdirk2_small_rate(gm, counts, torch, np, dev, default_options, sample_states
         best = min(best, time.perf_counter() - a)
     steps = int(cnt[0].sum().item())
     newton = int(cnt[2].sum().item())
-    it = counts.sdirk2_iteration()
-    guess = counts.source()
-    flops = it.flops * newton + guess.flops * (steps + n)
-    r = {"workload": f"h2like_10_27, {n} cells, T0~U[1000,1500] K, Dirichlet(1), SDIRK-2 100 x 2e-7 s, persistent",
+    failed = int((st != 0).sum().item())
+    it = counts.sdirk_iteration()
+    # the guess S(y_n) once per step begun (completed steps plus a failed cell's last), the stage
+    # bases and y_{n+1} once per completed step
+    flops = (it.flops * newton + counts.sdirk_step_combination(stages).flops * steps
+             + counts.source().flops * (steps + failed))
+    r = {"workload": f"h2like_10_27, {n} cells, T0~U[1000,1500] K, Dirichlet(1), {label} 100 x 2e-7 s, persistent",
          "ms": best * 1e3, "cell_substeps_per_s": steps / best, "newton_iterations": newton,
          "flops_per_newton_iteration": it.flops, "tflops_algorithmic": flops / best / 1e12,
-         "failed_cells": int((st != 0).sum().item()), "launch": list(gm.chem_get_launch(CHEM_SDIRK2, CHEM_PERSISTENT))}
-    log(f"SDIRK-2 1024 cells: {best * 1e3:.2f} ms, {steps / best:.3e} cell-substeps/s, {newton} Newton iterations, "
+         "failed_cells": failed, "launch": list(gm.chem_get_launch(method, CHEM_PERSISTENT))}
+    log(f"{label} 1024 cells: {best * 1e3:.2f} ms, {steps / best:.3e} cell-substeps/s, {newton} Newton iterations, "
         f"{flops / best / 1e12:.2f} TFLOP/s algorithmic, failed cells {r['failed_cells']}")
     return r
 

@@ -61,7 +61,7 @@ enum {
   CHEM_CELL_T_RANGE = 5        /* input temperature <= 0 */
 };
 
-enum { CHEM_BE = 0, CHEM_ROS2 = 1, CHEM_SDIRK2 = 2 };
+enum { CHEM_BE = 0, CHEM_ROS2 = 1, CHEM_SDIRK2 = 2, CHEM_SDIRK4 = 3 };
 enum { CHEM_CONST_P = 0, CHEM_CONST_V = 1 };
 enum { CHEM_PERSISTENT = 0, CHEM_PLAIN = 1 };
 enum { CHEM_FLAG_CHECK_CELLS = 1 };  /* synchronise and return CHEM_ECELLS if a cell failed */
@@ -81,6 +81,11 @@ enum { CHEM_FLAG_CHECK_CELLS = 1 };  /* synchronise and return CHEM_ECELLS if a 
  *                    the state change gamma h delta in the Newton test below.  A failed step sets
  *                    CHEM_CELL_NEWTON_FAIL (no halving).  Persistent form only, n <= 24 only, no
  *                    adjoint tape; counters: completed steps, 0, Newton iterations.
+ *           CHEM_SDIRK4: the five-stage, fourth-order, stiffly accurate SDIRK of Appendix A.2
+ *                    (a_ii = 4/15; the tableau's 7-digit values as printed, a_52 = b_2).  Stage p
+ *                    solves Gamma_p = S(y_n + h sum_{j<p} a_pj Gamma_j + a_pp h Gamma_p) by Newton
+ *                    as for CHEM_SDIRK2; y_{n+1} = y_n + h sum_p b_p Gamma_p.  Same restrictions,
+ *                    failure status and counters as CHEM_SDIRK2.
  *  energy   CHEM_CONST_P: omega_T = -sum H_i omega_i / sum C_i Cp_i (Appendix B)
  *           CHEM_CONST_V: omega_T = -sum U_i omega_i / sum C_i Cv_i (Section 3)
  *  form     CHEM_PERSISTENT: one persistent kernel, cells pulled from a work queue lane by lane.

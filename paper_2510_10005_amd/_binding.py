@@ -15,7 +15,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_PKG, "libchem.so")
 
 CHEM_OK = 0
-CHEM_BE, CHEM_ROS2, CHEM_SDIRK2 = 0, 1, 2
+CHEM_BE, CHEM_ROS2, CHEM_SDIRK2, CHEM_SDIRK4 = 0, 1, 2, 3
 CHEM_CONST_P, CHEM_CONST_V = 0, 1
 CHEM_PERSISTENT, CHEM_PLAIN = 0, 1
 CHEM_FLAG_CHECK_CELLS = 1

@@ -55,18 +55,27 @@ const char* kKernelNames[] = {
     "chem_k_ros2_persistent", "chem_k_ros2_init",       "chem_k_ros2_step",        "chem_k_be_persistent",
     "chem_k_be_init",       "chem_k_be_step",          "chem_k_be_adjoint",       "chem_k_reduce_blocks",
     "chem_k_sched_scan",    "chem_k_sched_scatter",    "chem_k_jac_transpose",    "chem_k_ros2_persistent_rec",
-    "chem_k_ros2_adjoint",  "chem_k_sdirk2_persistent"};
+    "chem_k_ros2_adjoint",  "chem_k_sdirk2_persistent", "chem_k_sdirk4_persistent"};
 enum KernelId {
   K_THERMO, K_SOURCE, K_JACOBIAN, K_TPY, K_MASSFRAC, K_TPY_VJP, K_MASSFRAC_VJP, K_FILL_U64,
   K_ROS2_PERSISTENT, K_ROS2_INIT, K_ROS2_STEP, K_BE_PERSISTENT, K_BE_INIT, K_BE_STEP, K_BE_ADJOINT,
   K_REDUCE_BLOCKS, K_SCHED_SCAN, K_SCHED_SCATTER, K_JAC_TRANSPOSE, K_ROS2_PERSISTENT_REC, K_ROS2_ADJOINT,
-  K_SDIRK2_PERSISTENT, K_COUNT
+  K_SDIRK2_PERSISTENT, K_SDIRK4_PERSISTENT, K_COUNT
 };
 // kernels that only the register-resident form (n <= kDenseLimit) has
-bool dense_only(int k) { return k == K_ROS2_PERSISTENT_REC || k == K_ROS2_ADJOINT || k == K_SDIRK2_PERSISTENT; }
+bool dense_only(int k) {
+  return k == K_ROS2_PERSISTENT_REC || k == K_ROS2_ADJOINT || k == K_SDIRK2_PERSISTENT || k == K_SDIRK4_PERSISTENT;
+}
 // persistent integration kernel of a method
+bool known_method(int m) { return m == CHEM_BE || m == CHEM_ROS2 || m == CHEM_SDIRK2 || m == CHEM_SDIRK4; }
+bool sdirk(int m) { return m == CHEM_SDIRK2 || m == CHEM_SDIRK4; }
 KernelId persistent_kernel(int method) {
-  return method == CHEM_ROS2 ? K_ROS2_PERSISTENT : (method == CHEM_SDIRK2 ? K_SDIRK2_PERSISTENT : K_BE_PERSISTENT);
+  switch (method) {
+    case CHEM_ROS2: return K_ROS2_PERSISTENT;
+    case CHEM_SDIRK2: return K_SDIRK2_PERSISTENT;
+    case CHEM_SDIRK4: return K_SDIRK4_PERSISTENT;
+    default: return K_BE_PERSISTENT;
+  }
 }
 constexpr int kSchedBins = 256;  // CHEM_SCHED_BINS in the device code
 
@@ -125,7 +134,7 @@ std::vector<std::string> compile_options(const std::string& arch) {
 // a larger one is split into one program per group, compiled concurrently, because its code is
 // large enough that a single compile is slow.
 constexpr int kGroups = 4;
-const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1, 0, 1, 3, 2};
+const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1, 0, 1, 3, 2, 2};
 
 struct CodeObject {
   std::string code, path;
@@ -262,8 +271,8 @@ struct chem_mech {
   bool wave = false;  // one cell per 64-lane wavefront (blocks of 64)
   DevBuf lnA_default, queue, ws, wst, counters_internal, running, seg, gws, gpart, sched, order, jstage;
   unsigned int* running_host = nullptr;
-  int launch_block[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // [method][form]
-  int launch_grid[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  int launch_block[4][2] = {};  // [method][form]
+  int launch_grid[4][2] = {};
   std::mutex mu;
   ~chem_mech() {
     if (running_host) (void)hipHostFree(running_host);
@@ -326,7 +335,7 @@ DevChemOpts to_dev(const chem_integrator_opts& o, int ckpt_every) {
 
 chem_err validate_opts(const chem_integrator_opts* o) {
   if (!o) return fail(CHEM_EINVAL, "null options");
-  if (o->method != CHEM_BE && o->method != CHEM_ROS2 && o->method != CHEM_SDIRK2)
+  if (!known_method(o->method))
     return fail(CHEM_EINVAL, "unknown method");
   if (o->energy != CHEM_CONST_P && o->energy != CHEM_CONST_V) return fail(CHEM_EINVAL, "unknown energy mode");
   if (o->form != CHEM_PERSISTENT && o->form != CHEM_PLAIN) return fail(CHEM_EINVAL, "unknown form");
@@ -617,9 +626,9 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
   if (chem_err e = check_cells(M, n, ld)) return e;
   if (chem_err e = validate_opts(opts)) return e;
   if (M->wave) return fail(CHEM_EUNSUPPORTED, kWaveIntegrationOff);
-  if (opts->method == CHEM_SDIRK2) {
-    if (opts->form != CHEM_PERSISTENT) return fail(CHEM_EUNSUPPORTED, "SDIRK-2 runs in the persistent form");
-    if (tape) return fail(CHEM_EUNSUPPORTED, "no adjoint tape for SDIRK-2");
+  if (sdirk(opts->method)) {
+    if (opts->form != CHEM_PERSISTENT) return fail(CHEM_EUNSUPPORTED, "SDIRK schemes run in the persistent form");
+    if (tape) return fail(CHEM_EUNSUPPORTED, "no adjoint tape for the SDIRK schemes");
   }
   if (tape) {
     if (tape->mech != M) return fail(CHEM_EINVAL, "tape belongs to another mechanism");
@@ -688,7 +697,7 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
     }
     uint64_t* q = M->queue.as<uint64_t>();
     if ((e = fill_u64(M, q, 1, 0, s))) return e;
-    if (method == CHEM_SDIRK2) {
+    if (sdirk(method)) {
       void* args[] = {&n, &ld, &y, &la, &o, &status, &cnt, &q};
       if ((e = launch(M, k, grid, block, s, args))) return e;
     } else if (method == CHEM_ROS2) {
@@ -868,7 +877,7 @@ chem_err chem_integrate_adjoint(const chem_mech* Mc, chem_tape* tape, const doub
 
 chem_err chem_set_launch(chem_mech* M, int method, int form, int block, int grid) {
   if (!M) return fail(CHEM_EINVAL, "null mechanism");
-  if ((method != CHEM_BE && method != CHEM_ROS2 && method != CHEM_SDIRK2) ||
+  if (!known_method(method) ||
       (form != CHEM_PERSISTENT && form != CHEM_PLAIN))
     return fail(CHEM_EINVAL, "unknown method or form");
   if (block != 0 && (block < 64 || block > kMaxBlock || block % 64)) return fail(CHEM_EINVAL, "block must be 64..256, a multiple of 64");
@@ -880,7 +889,7 @@ chem_err chem_set_launch(chem_mech* M, int method, int form, int block, int grid
 
 chem_err chem_get_launch(const chem_mech* M, int method, int form, int* block, int* grid) {
   if (!M || !block || !grid) return fail(CHEM_EINVAL, "null argument");
-  if ((method != CHEM_BE && method != CHEM_ROS2 && method != CHEM_SDIRK2) ||
+  if (!known_method(method) ||
       (form != CHEM_PERSISTENT && form != CHEM_PLAIN))
     return fail(CHEM_EINVAL, "unknown method or form");
   if (form == CHEM_PERSISTENT) {

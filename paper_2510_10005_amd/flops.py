@@ -161,15 +161,23 @@ class MechanismCounts:
         c.flops += 6                                                # controller
         return c
 
-    def sdirk2_iteration(self) -> Count:
-        """One Newton iteration of an SDIRK-2 stage on the active system (the initial guess S(y_n)
-        of each step is one source() evaluation, counted by the caller)."""
+    def sdirk_iteration(self) -> Count:
+        """One Newton iteration of an SDIRK stage (Appendix A.1, A.2) on the active system (the
+        initial guess S(y_n) of each step is one source() evaluation, counted by the caller)."""
         n, ns = self.na, self.ns
         c = self.jacobian(reduced=True) + self.lu() + self.solve()
         c.flops += 2 * n + 1 + n                                    # stage state b + gamma h Gamma, gamma h
         c.flops += n + n * n + n                                    # residual, G = I - gamma h J
         c.flops += 2 * n + n + 5 * ns + 3                           # update, scaled norm
         return c
+
+    def sdirk_step_combination(self, stages: int) -> Count:
+        """Per completed SDIRK step: the stage bases b_p = y_n + sum_{j<p} (h a_pj) Gamma_j and
+        y_{n+1} = y_n + sum_p (h b_p) Gamma_p on the active components (one multiply and one add
+        per term; the products h a_pj and h b_p once each)."""
+        n = self.na
+        terms = stages * (stages - 1) // 2 + stages
+        return Count(flops=2 * n * terms + terms + 1)
 
     def be_iteration(self) -> Count:
         n, ns = self.na, self.ns
@@ -182,6 +190,6 @@ class MechanismCounts:
 if __name__ == "__main__":
     import sys
     m = MechanismCounts(sys.argv[1])
-    for name in ("source", "jacobian", "lu", "ros2_attempt", "be_iteration", "sdirk2_iteration"):
+    for name in ("source", "jacobian", "lu", "ros2_attempt", "be_iteration", "sdirk_iteration"):
         v = getattr(m, name)()
         print(f"{name:14s} flops {v.flops:10.0f}  T-ops {v.tops:6.0f}")

@@ -1,9 +1,12 @@
 """GPU: SDIRK-2 (Appendix A.1, persistent form) against the oracle, cell by cell.
 
 Statuses and completed steps must equal the oracle's, states within 1e-8 (relative, species as
-mass fractions).  Newton iteration counts must agree within one iteration, and exactly for at
-least 97 % of the cells: the convergence test max |gamma h delta| / sc <= 1 can flip between two
-correct answers when the norm lands within rounding of 1 (the LU's rounding order differs).
+mass fractions).  Newton iteration counts of converged cells must agree within one iteration, and
+exactly for at least 97 % of them: the convergence test max |gamma h delta| / sc <= 1 can flip
+between two correct answers when the norm lands within rounding of 1 (the LU's rounding order
+differs).  In a failed cell the failing stage's iteration does not converge and the iteration at
+which its norm first grows depends on rounding, so there the counts may differ by up to
+newton_max - 1.
 Cases: the backward-Euler workload's states at the paper's SDIRK-2 step (7e-7 s) and at
 4 x 5e-7 s, the Rosenbrock workload's states at 5 x 2e-8 s, both energy modes, Newton failure (newton_max = 1), argument errors, the autotuned launch, and
 sampled cells of the 1024-cell workload over its 2e-5 s at the paper's step size.
@@ -43,9 +46,11 @@ def _run(gm, om, y0, dt, n_steps, ld=None, **kw):
     return host_aos(y, nc), st.cpu().numpy()[:nc], cnt.cpu().numpy()[:, :nc]
 
 
-def _check_newton(got, ref):
+def _check_newton(got, ref, status, newton_max=IntegratorOptions().newton_max):
     d = np.abs(got.astype(np.int64) - ref.astype(np.int64))
-    assert d.max() <= 1 and (d == 0).mean() >= 0.97, (got, ref)
+    ok = status == 0
+    assert d[ok].max(initial=0) <= 1 and (not ok.any() or (d[ok] == 0).mean() >= 0.97), (got[ok], ref[ok])
+    assert d[~ok].max(initial=0) <= newton_max - 1, (got[~ok], ref[~ok])
 
 
 CASES = {
@@ -68,7 +73,7 @@ def test_sdirk2_matches_oracle(mechs, case):
     got, st, cnt = _run(gm, om, y0, dt, n_steps, energy=energy)
     np.testing.assert_array_equal(st, ref["status"])
     np.testing.assert_array_equal(cnt[0], ref["steps"])
-    _check_newton(cnt[2], ref["newton"])
+    _check_newton(cnt[2], ref["newton"], ref["status"])
     ok = ref["status"] == 0
     err = integrated_state_error(om, got[ok], ref["y"][ok])
     print(f"[gpu] SDIRK-2 {case}: {ok.sum()} cells, max rel err {err.max():.2e}", flush=True)
@@ -119,7 +124,7 @@ def test_sdirk2_fullsize_sampled_cells_autotuned():
     ref = oracle.integrate_sdirk2(om, y0[idx], 2e-5, 29)
     got = yd[:, idx].cpu().numpy().T
     np.testing.assert_array_equal(st.cpu().numpy()[idx], ref["status"])
-    _check_newton(cnt[2].cpu().numpy()[idx], ref["newton"])
+    _check_newton(cnt[2].cpu().numpy()[idx], ref["newton"], ref["status"])
     err = integrated_state_error(om, got, ref["y"])
     print(f"[gpu] full-size SDIRK-2: max rel err {err.max():.2e}", flush=True)
     assert err.max() <= 1e-8
