@@ -7,7 +7,8 @@ eqs. for q_j, K_j, the Arrhenius, third-body and Troe forms), the
 temperature source under constant volume (Section 3, eq.
 temperature_source) or constant pressure (Appendix B), the analytic
 source Jacobian (Section 3.2), backward Euler with Newton (Section 3.2),
-the SDIRK schemes (two and five stages, Appendix A.1/A.2) and the
+the SDIRK schemes (two and five stages, Appendix A.1/A.2), YASS (Appendix
+A.4) with an LU or Jacobi-preconditioned GMRES solve (Section 3.4) and the
 two-stage Rosenbrock scheme (Appendix A.3), plus forward and
 reverse sensitivities of the backward-Euler map and the discrete adjoint
 of the Rosenbrock map along its accepted step sequence.
@@ -33,6 +34,8 @@ from .kinetics import (  # noqa: F401
 )
 from .integrate import (  # noqa: F401
     CELL_OK, CELL_NEWTON_FAIL, CELL_DT_UNDERFLOW, CELL_MAX_STEPS, CELL_NONFINITE, CELL_T_RANGE,
-    IntegratorOptions, state_from_TPY, mass_fractions, integrate_be, integrate_ros2, integrate_sdirk2, integrate_sdirk4,
+    LINSOLVE_LU, LINSOLVE_GMRES, IntegratorOptions, state_from_TPY, mass_fractions, integrate_be, integrate_ros2,
+    integrate_sdirk2, integrate_sdirk4, integrate_yass,
 )
+from .linsolve import gmres  # noqa: F401
 from .sensitivity import be_tangent, be_adjoint, ros2_replay, ros2_adjoint, ros2_adjoint_cell  # noqa: F401

@@ -9,6 +9,10 @@
 * ``integrate_sdirk2`` / ``integrate_sdirk4``: the two-stage SDIRK scheme of Appendix A.1
   (gamma = 1 - sqrt(2)/2) and the five-stage one of Appendix A.2 at fixed steps, each stage
   solved by full Newton from the initial guess S(y_n).
+* ``integrate_yass``: YASS (Appendix A.4): one linearised backward-Euler solve
+  (I - h J(y_n)) dy = h S(y_n) per substep, the substep halved while the decrement is larger
+  than alpha, failure once it would fall below h_min; the solve by LU or by Jacobi-preconditioned
+  GMRES (Section 3.4, ``oracle.linsolve``).
 * ``integrate_ros2``: the two-stage Rosenbrock method of Appendix A.3 with
   gamma = 1 + sqrt(2)/2, alpha = 1/gamma, beta = -2/gamma, m1 = 3/(2 gamma),
   m2 = 1/(2 gamma); the second stage right-hand side is S(y + alpha G1) + (beta/h) G1
@@ -28,9 +32,11 @@ from dataclasses import dataclass
 import numpy as np
 
 from .kinetics import CONST_P, jacobian, source_terms
+from .linsolve import gmres
 from .mechanism import R
 
 CELL_OK, CELL_NEWTON_FAIL, CELL_DT_UNDERFLOW, CELL_MAX_STEPS, CELL_NONFINITE, CELL_T_RANGE = range(6)
+LINSOLVE_LU, LINSOLVE_GMRES = 0, 1
 
 ROS2_GAMMA = 1.0 + math.sqrt(2.0) / 2.0
 ROS2_ALPHA = 1.0 / ROS2_GAMMA
@@ -56,6 +62,13 @@ class IntegratorOptions:
     fac_min: float = 0.2
     fac_max: float = 5.0
     safety: float = 0.9
+    # YASS (Appendix A.4) and its linear solver (Section 3.4)
+    yass_alpha: float = 0.1         # bound on max(|dT|/T, max_i |dY_i|) per substep
+    linear_solver: int = 0          # LINSOLVE_LU or LINSOLVE_GMRES
+    krylov_dim: int = 0             # GMRES restart length (0: the system size)
+    krylov_rtol: float = 1e-10      # on the preconditioned residual, relative to |M^-1 b|
+    krylov_max_iter: int = 100
+    krylov_jacobi: bool = True      # M = diag(A), else M = I
 
 
 def state_from_TPY(mech, T, p, Y):
@@ -352,6 +365,94 @@ def integrate_sdirk4(mech, y0, dt_total, n_steps, lnA=None, opt=None):
 
 
 # ----------------------------------------------------------------------------- Rosenbrock
+
+def yass_norm(mech, y, dy, rho):
+    """Size of a YASS decrement: max(|dT| / T, max_i |dC_i| W_i / rho), the relative change of T
+    and the absolute change of the mass fractions (rho from the cell's initial state)."""
+    dT = np.abs(dy[:, 0]) / y[:, 0]
+    dY = np.abs(dy[:, 1:]) * mech.W[None, :] / rho[:, None]
+    return np.maximum(dT, dY.max(axis=1))
+
+
+def _linear_solve(A, b, opt):
+    """One solve of A x = b (single system): LU with partial pivoting (LAPACK) or GMRES.
+    Returns (x, Krylov iterations)."""
+    if opt.linear_solver == LINSOLVE_GMRES:
+        x, its, _ = gmres(A, b, opt.krylov_dim, opt.krylov_rtol, opt.krylov_max_iter, opt.krylov_jacobi)
+        return x, its
+    return np.linalg.solve(A, b), 0
+
+
+def integrate_yass(mech, y0, dt_total, n_steps, lnA=None, opt=None):
+    """YASS (Appendix A.4) over ``n_steps`` fixed steps of dt_total/n_steps for every cell.
+
+    Each fixed step starts with the substep h = dt_total/n_steps.  An attempt solves
+    (I - h J(y)) dy = h S(y) at the current state y (one linearised backward-Euler step).  It is
+    accepted when dy, y + dy are finite, T + dT > 0 and yass_norm(dy) <= yass_alpha: then
+    y <- y + dy.  Otherwise the substep is halved (h <- h/2) and the attempt repeated; if the halved
+    substep is below h_min the cell fails with CELL_DT_UNDERFLOW.  A halved substep is kept until
+    the fixed step is covered (the remaining time is always a whole number of substeps); the next
+    fixed step starts again from dt_total/n_steps.  A cell that uses up max_steps attempts stops
+    with CELL_MAX_STEPS.  A failed cell keeps its last accepted state.
+    Returns dict(y, status, accepted, rejected, krylov) (Krylov iterations summed over attempts,
+    0 with the LU solver)."""
+    opt = opt or IntegratorOptions()
+    y = np.array(y0, dtype=float, copy=True)
+    nc, n = y.shape
+    status = _input_status(y)
+    rho = (y[:, 1:] * mech.W[None, :]).sum(axis=1)
+    h0 = dt_total / n_steps
+    step = np.zeros(nc, dtype=np.int64)
+    depth = np.zeros(nc, dtype=np.int64)
+    done_sub = np.zeros(nc, dtype=np.int64)      # substeps taken in this fixed step, at this depth
+    acc = np.zeros(nc, dtype=np.int64)
+    rej = np.zeros(nc, dtype=np.int64)
+    kry = np.zeros(nc, dtype=np.int64)
+    active = status == CELL_OK
+    eye = np.eye(n)
+    while active.any():
+        idx = np.nonzero(active)[0]
+        h = h0 * np.exp2(-depth[idx].astype(float))
+        with np.errstate(all="ignore"):
+            S = source_terms(mech, y[idx], lnA, opt.energy)
+            J = jacobian(mech, y[idx], lnA, opt.energy)
+            dy = np.full((idx.size, n), np.nan)
+            for c in range(idx.size):
+                try:
+                    dy[c], its = _linear_solve(eye - h[c] * J[c], h[c] * S[c], opt)
+                    kry[idx[c]] += its
+                except np.linalg.LinAlgError:
+                    pass
+            ynew = y[idx] + dy
+            norm = yass_norm(mech, y[idx], dy, rho[idx])
+        ok = (np.all(np.isfinite(dy), axis=1) & np.all(np.isfinite(ynew), axis=1) & (ynew[:, 0] > 0.0)
+              & (norm <= opt.yass_alpha))
+        att = acc[idx] + rej[idx] + 1
+        for c, cell in enumerate(idx):
+            if ok[c]:
+                y[cell] = ynew[c]
+                acc[cell] += 1
+                done_sub[cell] += 1
+                if done_sub[cell] == (1 << int(depth[cell])):
+                    step[cell] += 1
+                    depth[cell] = 0
+                    done_sub[cell] = 0
+                    if step[cell] == n_steps:
+                        active[cell] = False
+                        continue
+            else:
+                rej[cell] += 1
+                depth[cell] += 1
+                done_sub[cell] *= 2
+                if h[c] * 0.5 < opt.h_min or depth[cell] > 60:
+                    status[cell] = CELL_DT_UNDERFLOW
+                    active[cell] = False
+                    continue
+            if att[c] >= opt.max_steps:
+                status[cell] = CELL_MAX_STEPS
+                active[cell] = False
+    return dict(y=y, status=status, accepted=acc, rejected=rej, krylov=kry)
+
 
 def _ros2_scales(mech, y_a, y_b, rho, opt):
     """Error weights: T: rtol max(|T_a|,|T_b|) + atol; species in mass-fraction space."""
