@@ -66,9 +66,10 @@ class IntegratorOptions:
     yass_alpha: float = 0.1         # bound on max(|dT|/T, max_i |dY_i|) per substep
     linear_solver: int = 0          # LINSOLVE_LU or LINSOLVE_GMRES
     krylov_dim: int = 0             # GMRES restart length (0: the system size)
-    krylov_rtol: float = 1e-10      # on the preconditioned residual, relative to |M^-1 b|
+    krylov_rtol: float = 1e-12      # on the preconditioned residual, relative to |M^-1 b|
     krylov_max_iter: int = 100
     krylov_jacobi: bool = True      # M = diag(A), else M = I
+    krylov_lsq: str = "lstsq"       # GMRES least-squares solve: "lstsq" or "givens"
 
 
 def state_from_TPY(mech, T, p, Y):
@@ -378,7 +379,8 @@ def _linear_solve(A, b, opt):
     """One solve of A x = b (single system): LU with partial pivoting (LAPACK) or GMRES.
     Returns (x, Krylov iterations)."""
     if opt.linear_solver == LINSOLVE_GMRES:
-        x, its, _ = gmres(A, b, opt.krylov_dim, opt.krylov_rtol, opt.krylov_max_iter, opt.krylov_jacobi)
+        x, its, _ = gmres(A, b, opt.krylov_dim, opt.krylov_rtol, opt.krylov_max_iter, opt.krylov_jacobi,
+                          opt.krylov_lsq)
         return x, its
     return np.linalg.solve(A, b), 0
 

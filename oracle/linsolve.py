@@ -10,8 +10,13 @@ Steps of one cycle, from the current iterate x (x0 = 0):
   r0 = M^-1 (b - A x), beta = |r0|, v_1 = r0 / beta;
   Arnoldi with modified Gram-Schmidt: w = M^-1 A v_j; h_ij = (w, v_i), w -= h_ij v_i for i <= j;
   h_{j+1,j} = |w|, v_{j+1} = w / h_{j+1,j};
-  y_j = argmin |beta e_1 - Hbar_j y| (the (j+1) x j Hessenberg matrix), taken here from
-  numpy.linalg.lstsq, whose residual is |M^-1 (b - A (x + V_j y_j))|.
+  y_j = argmin |beta e_1 - Hbar_j y| (the (j+1) x j Hessenberg matrix), whose residual is
+  |M^-1 (b - A (x + V_j y_j))|.  Two textbook ways to solve that small least-squares problem
+  are offered: numpy.linalg.lstsq on Hbar_j (``lsq="lstsq"``), or Givens rotations applied to
+  each new column of Hbar_j as it is formed, with |g_{j+1}| as the residual and back substitution
+  on the rotated triangle (``lsq="givens"``).  They agree in exact arithmetic; on badly scaled
+  systems their rounding differs visibly, which the tests use to measure how well the iterate is
+  determined.
 The solve stops when that residual is <= rtol |M^-1 b|, after max_iter iterations in all, or at a
 happy breakdown (h_{j+1,j} = 0: the Krylov space is invariant and x + V_j y_j is exact).  After m
 iterations without stopping the cycle restarts from x + V_m y_m.
@@ -22,9 +27,27 @@ from __future__ import annotations
 import numpy as np
 
 
-def gmres(A, b, m, rtol, max_iter, jacobi=True):
+def _givens_cycle_solve(H, beta, j):
+    """min |beta e_1 - H[:j+2, :j+1] y| by Givens rotations (column by column) and back
+    substitution; returns (y, residual)."""
+    R = H[:j + 2, :j + 1].copy()
+    g = np.zeros(j + 2)
+    g[0] = beta
+    for i in range(j + 1):
+        den = np.hypot(R[i, i], R[i + 1, i])
+        c, s = R[i, i] / den, R[i + 1, i] / den
+        Ri, Ri1 = R[i, :].copy(), R[i + 1, :].copy()
+        R[i, :], R[i + 1, :] = c * Ri + s * Ri1, -s * Ri + c * Ri1
+        g[i], g[i + 1] = c * g[i] + s * g[i + 1], -s * g[i] + c * g[i + 1]
+    y = np.zeros(j + 1)
+    for i in range(j, -1, -1):
+        y[i] = (g[i] - R[i, i + 1:j + 1] @ y[i + 1:]) / R[i, i]
+    return y, abs(g[j + 1])
+
+
+def gmres(A, b, m, rtol, max_iter, jacobi=True, lsq="lstsq"):
     """Restarted GMRES(m) for one system A x = b ([n, n], [n]).  Returns (x, iterations, converged).
-    m <= 0 means m = n (no restart)."""
+    m <= 0 means m = n (no restart); ``lsq`` picks the least-squares solve ("lstsq" or "givens")."""
     A = np.asarray(A, dtype=float)
     b = np.asarray(b, dtype=float)
     n = b.shape[0]
@@ -53,10 +76,13 @@ def gmres(A, b, m, rtol, max_iter, jacobi=True):
                 w = w - H[i, j] * V[:, i]
             H[j + 1, j] = np.linalg.norm(w)
             its += 1
-            e1 = np.zeros(j + 2)
-            e1[0] = beta
-            y = np.linalg.lstsq(H[:j + 2, :j + 1], e1, rcond=None)[0]
-            res = np.linalg.norm(e1 - H[:j + 2, :j + 1] @ y)
+            if lsq == "givens":
+                y, res = _givens_cycle_solve(H, beta, j)
+            else:
+                e1 = np.zeros(j + 2)
+                e1[0] = beta
+                y = np.linalg.lstsq(H[:j + 2, :j + 1], e1, rcond=None)[0]
+                res = np.linalg.norm(e1 - H[:j + 2, :j + 1] @ y)
             breakdown = H[j + 1, j] == 0.0
             if res <= target or breakdown or its >= max_iter:
                 return x + V[:, :j + 1] @ y, its, bool(res <= target or breakdown)

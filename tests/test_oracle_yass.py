@@ -6,7 +6,8 @@ GMRES (oracle.linsolve.gmres):
   a brute-force least-squares fit over the explicitly formed basis [c, Bc, ..., B^(j-1) c];
 * Jacobi preconditioning solves a diagonal system in one iteration; without it a diagonal system
   with k distinct entries needs exactly k (the degree of the minimal polynomial);
-* GMRES(1) is the minimal-residual iteration x <- x + (r.Br / Br.Br) r.
+* GMRES(1) is the minimal-residual iteration x <- x + (r.Br / Br.Br) r;
+each with both least-squares solves of the Hessenberg problem (LAPACK lstsq and Givens rotations).
 
 YASS (oracle.integrate_yass):
 * on the linear isomerisation A <=> B (T constant) one accepted substep is (I - hK)^-1 C exactly,
@@ -34,17 +35,22 @@ def _random_system(n, seed, cond_shift=4.0):
     return A, rng.standard_normal(n)
 
 
+LSQ = ["lstsq", "givens"]
+
+
+@pytest.mark.parametrize("lsq", LSQ)
 @pytest.mark.parametrize("jacobi", [True, False])
-def test_gmres_full_space_equals_lapack(jacobi):
+def test_gmres_full_space_equals_lapack(jacobi, lsq):
     for seed in range(5):
         A, b = _random_system(8, seed)
-        x, its, conv = gmres(A, b, 0, 1e-15, 50, jacobi)
+        x, its, conv = gmres(A, b, 0, 1e-15, 50, jacobi, lsq)
         assert conv and its <= 2 * 8       # n, and at most one short restart at the rounding floor
         ref = np.linalg.solve(A, b)
         assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-def test_gmres_on_chemistry_iteration_matrix(mech_small):
+@pytest.mark.parametrize("lsq", LSQ)
+def test_gmres_on_chemistry_iteration_matrix(mech_small, lsq):
     """I - hJ of a synthetic mechanism (badly scaled: T next to concentrations)."""
     m = mech_small
     T, p, Y = sample_config("be_small", m.ns, 3)
@@ -55,19 +61,20 @@ def test_gmres_on_chemistry_iteration_matrix(mech_small):
         h = 1e-7
         A = np.eye(m.n) - h * J[c]
         b = h * S[c]
-        x, its, conv = gmres(A, b, 0, 1e-15, 100, True)
+        x, its, conv = gmres(A, b, 0, 1e-15, 100, True, lsq)
         ref = np.linalg.solve(A, b)
         assert conv
         assert np.abs(x - ref).max() <= 1e-8 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("lsq", LSQ)
 @pytest.mark.parametrize("jacobi", [True, False])
-def test_gmres_iterates_minimise_the_residual_over_krylov_space(jacobi):
+def test_gmres_iterates_minimise_the_residual_over_krylov_space(jacobi, lsq):
     A, b = _random_system(8, 11, cond_shift=3.0)
     dinv = 1.0 / np.diag(A) if jacobi else np.ones(8)
     B, c = dinv[:, None] * A, dinv * b
     for j in range(1, 5):
-        x, its, _ = gmres(A, b, 0, 0.0, j, jacobi)
+        x, its, _ = gmres(A, b, 0, 0.0, j, jacobi, lsq)
         assert its == j
         K = np.stack([np.linalg.matrix_power(B, i) @ c for i in range(j)], axis=1)
         z = np.linalg.lstsq(B @ K, c, rcond=None)[0]
@@ -76,26 +83,28 @@ def test_gmres_iterates_minimise_the_residual_over_krylov_space(jacobi):
         assert np.abs(x - x_ref).max() <= 1e-9 * np.abs(x_ref).max()
 
 
-def test_gmres_diagonal_systems():
+@pytest.mark.parametrize("lsq", LSQ)
+def test_gmres_diagonal_systems(lsq):
     d = np.array([2.0, 2.0, 5.0, 5.0, 5.0, -3.0, 2.0])
     A = np.diag(d)
     b = np.arange(1.0, 8.0)
-    x, its, conv = gmres(A, b, 0, 1e-14, 50, True)
+    x, its, conv = gmres(A, b, 0, 1e-14, 50, True, lsq)
     assert conv and its == 1
     np.testing.assert_allclose(x, b / d, rtol=1e-15)
-    x, its, conv = gmres(A, b, 0, 1e-14, 50, False)
+    x, its, conv = gmres(A, b, 0, 1e-14, 50, False, lsq)
     assert conv and its == 3
     np.testing.assert_allclose(x, b / d, rtol=1e-13)
 
 
-def test_gmres_restart_one_is_minimal_residual_iteration():
+@pytest.mark.parametrize("lsq", LSQ)
+def test_gmres_restart_one_is_minimal_residual_iteration(lsq):
     A, b = _random_system(6, 3, cond_shift=6.0)
     x_ref = np.zeros(6)
     for _ in range(2):
         r = b - A @ x_ref
         Ar = A @ r
         x_ref = x_ref + (r @ Ar) / (Ar @ Ar) * r
-    x, its, _ = gmres(A, b, 1, 0.0, 2, False)
+    x, its, _ = gmres(A, b, 1, 0.0, 2, False, lsq)
     assert its == 2
     np.testing.assert_allclose(x, x_ref, rtol=1e-12)
 
