@@ -155,6 +155,9 @@ def main():
     for name, method in (("sdirk2_1024", CHEM_SDIRK2), ("sdirk4_1024", CHEM_SDIRK4)):
         extras[name] = sdirk_small_rate(gm, counts, method, torch, np, dev, default_options, sample_states,
                                         STATE_CONFIGS)
+    for name, solver in (("yass_lu_1024", 0), ("yass_gmres_1024", 1)):
+        extras[name] = yass_small_rate(gm, counts, solver, torch, np, dev, default_options, sample_states,
+                                       STATE_CONFIGS)
 
     if not args.skip_adjoint:
         extras["adjoint"] = adjoint_ratio(gm, torch, np, dev, Tape, default_options, CHEM_BE, sample_states,
@@ -316,6 +319,50 @@ def sdirk_small_rate(gm, counts, method, torch, np, dev, default_options, sample
          "failed_cells": failed, "launch": list(gm.chem_get_launch(method, CHEM_PERSISTENT))}
     log(f"{label} 1024 cells: {best * 1e3:.2f} ms, {steps / best:.3e} cell-substeps/s, {newton} Newton iterations, "
         f"{flops / best / 1e12:.2f} TFLOP/s algorithmic, failed cells {r['failed_cells']}")
+    return r
+
+
+def yass_small_rate(gm, counts, solver, torch, np, dev, default_options, sample_states, STATE_CONFIGS):
+    """YASS (Appendix A.4) on the 1,024-cell workload's states over its 2e-5 s at the paper's YASS
+    step (200 steps of 1e-7 s, Table 5), LU or Jacobi-preconditioned GMRES (Section 3.4), persistent
+    form, autotuned launch.  The algorithmic flop count is given for the LU solve (per attempt:
+    Jacobian, source, LU and one solve, plus forming I - hJ and the decrement test)."""
+    from paper_2510_10005_amd import CHEM_PERSISTENT, CHEM_YASS
+    label = "LU" if solver == 0 else "GMRES (Jacobi)"
+    cfg = STATE_CONFIGS["be_small"]
+    n = cfg.n_cells
+    T, p, Y = sample_states(gm.ns, n, cfg.seed, cfg.T_range, cfg.alpha, cfg.p)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    y0 = torch.empty((gm.n, n), dtype=torch.float64, device=dev)
+    gm.chem_state_from_TPY(n, n, t(T), t(p), t(Y.T), y0)
+    y = torch.empty_like(y0)
+    st = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt = torch.zeros((3, n), dtype=torch.int32, device=dev)
+    opts = default_options(method=CHEM_YASS, dt=2e-5, n_steps=200, form=CHEM_PERSISTENT, linear_solver=solver)
+    gm.chem_autotune(n, n, y0, None, opts)
+    best = 1e30
+    for _ in range(3):
+        y.copy_(y0)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        gm.chem_integrate(n, n, y, None, opts, None, st, cnt)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - a)
+    acc = int(cnt[0].sum().item())
+    rej = int(cnt[1].sum().item())
+    kry = int(cnt[2].sum().item())
+    r = {"workload": f"h2like_10_27, {n} cells, T0~U[1000,1500] K, Dirichlet(1), YASS 200 x 1e-7 s, {label}, "
+                     "alpha 0.1, persistent",
+         "ms": best * 1e3, "cell_substeps_per_s": acc / best, "accepted_substeps": acc, "rejected_attempts": rej,
+         "krylov_iterations": kry, "failed_cells": int((st != 0).sum().item()),
+         "launch": list(gm.chem_get_launch(CHEM_YASS, CHEM_PERSISTENT))}
+    if solver == 0:
+        na = counts.na
+        per = counts.jacobian(reduced=True) + counts.source() + counts.lu() + counts.solve()
+        flops = (per.flops + na * na + 2 * na + 3 * na) * (acc + rej)
+        r["tflops_algorithmic"] = flops / best / 1e12
+    log(f"YASS {label} 1024 cells: {best * 1e3:.2f} ms, {acc / best:.3e} accepted substeps/s, {rej} rejections, "
+        f"{kry} Krylov iterations, failed cells {r['failed_cells']}")
     return r
 
 

@@ -61,7 +61,9 @@ enum {
   CHEM_CELL_T_RANGE = 5        /* input temperature <= 0 */
 };
 
-enum { CHEM_BE = 0, CHEM_ROS2 = 1, CHEM_SDIRK2 = 2, CHEM_SDIRK4 = 3 };
+enum { CHEM_BE = 0, CHEM_ROS2 = 1, CHEM_SDIRK2 = 2, CHEM_SDIRK4 = 3, CHEM_YASS = 4 };
+enum { CHEM_LINSOLVE_LU = 0, CHEM_LINSOLVE_GMRES = 1 };
+enum { CHEM_PRECOND_NONE = 0, CHEM_PRECOND_JACOBI = 1 };
 enum { CHEM_CONST_P = 0, CHEM_CONST_V = 1 };
 enum { CHEM_PERSISTENT = 0, CHEM_PLAIN = 1 };
 enum { CHEM_FLAG_CHECK_CELLS = 1 };  /* synchronise and return CHEM_ECELLS if a cell failed */
@@ -86,6 +88,21 @@ enum { CHEM_FLAG_CHECK_CELLS = 1 };  /* synchronise and return CHEM_ECELLS if a 
  *                    solves Gamma_p = S(y_n + h sum_{j<p} a_pj Gamma_j + a_pp h Gamma_p) by Newton
  *                    as for CHEM_SDIRK2; y_{n+1} = y_n + h sum_p b_p Gamma_p.  Same restrictions,
  *                    failure status and counters as CHEM_SDIRK2.
+ *           CHEM_YASS: YASS of Appendix A.4 over n_steps fixed steps of dt/n_steps (0 means 1).  Each
+ *                    substep of size h solves the linearised backward-Euler step
+ *                    (I - h J(y)) dy = h S(y) once, with LU (linear_solver CHEM_LINSOLVE_LU) or
+ *                    restarted GMRES (CHEM_LINSOLVE_GMRES, Section 3.4; left preconditioning by
+ *                    M = diag(I - hJ) with CHEM_PRECOND_JACOBI, or none; stop when the Euclidean
+ *                    norm of the preconditioned residual is <= krylov_rtol |M^-1 b|, or after
+ *                    krylov_max_iter iterations; restart length krylov_dim, 0 = system size).
+ *                    The substep is accepted when dy is finite, T stays > 0 and
+ *                    max(|dT|/T, max_i |dY_i|) <= yass_alpha (dY: mass fractions); else it is
+ *                    halved, and a cell whose halved substep would be below h_min stops with
+ *                    CHEM_CELL_DT_UNDERFLOW.  A halved substep is kept until the fixed step is
+ *                    covered; every fixed step starts from dt/n_steps.  max_steps bounds the
+ *                    attempts (CHEM_CELL_MAX_STEPS).  Persistent form only, n <= 24 only, no
+ *                    adjoint tape; counters: accepted substeps, rejected attempts, Krylov
+ *                    iterations (0 with LU).
  *  energy   CHEM_CONST_P: omega_T = -sum H_i omega_i / sum C_i Cp_i (Appendix B)
  *           CHEM_CONST_V: omega_T = -sum U_i omega_i / sum C_i Cv_i (Section 3)
  *  form     CHEM_PERSISTENT: one persistent kernel, cells pulled from a work queue lane by lane.
@@ -118,11 +135,18 @@ typedef struct {
   double newton_atol_Y;
   int probe_attempts;
   int reserved_;  /* padding; keep 0 */
+  double yass_alpha;    /* CHEM_YASS: bound on the substep's change (see method) */
+  int linear_solver;    /* CHEM_YASS: CHEM_LINSOLVE_LU or CHEM_LINSOLVE_GMRES */
+  int krylov_dim;       /* GMRES restart length, 0 = the size of the solved system */
+  double krylov_rtol;   /* GMRES stop: preconditioned residual <= krylov_rtol |M^-1 b| */
+  int krylov_max_iter;  /* GMRES iterations per solve, over all restarts */
+  int krylov_precond;   /* CHEM_PRECOND_JACOBI or CHEM_PRECOND_NONE */
 } chem_integrator_opts;
 
 /* Defaults: BE, const-p, persistent, dt 1e-7, n_steps 0, max_steps 100000, rtol 1e-6, atol 1e-10,
  * h_min 1e-20, newton_max 10, halving_max_depth 8, newton_rtol 1e-10, newton_atol_T 1e-8 K,
- * newton_atol_Y 1e-14, probe_attempts 48. */
+ * newton_atol_Y 1e-14, probe_attempts 48, yass_alpha 0.1, linear_solver LU, krylov_dim 0,
+ * krylov_rtol 1e-12, krylov_max_iter 100, krylov_precond Jacobi. */
 void chem_default_options(chem_integrator_opts* opts);
 
 /* Human-readable name of an error code (static string, never NULL). */

@@ -15,7 +15,9 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_PKG, "libchem.so")
 
 CHEM_OK = 0
-CHEM_BE, CHEM_ROS2, CHEM_SDIRK2, CHEM_SDIRK4 = 0, 1, 2, 3
+CHEM_BE, CHEM_ROS2, CHEM_SDIRK2, CHEM_SDIRK4, CHEM_YASS = 0, 1, 2, 3, 4
+CHEM_LINSOLVE_LU, CHEM_LINSOLVE_GMRES = 0, 1
+CHEM_PRECOND_NONE, CHEM_PRECOND_JACOBI = 0, 1
 CHEM_CONST_P, CHEM_CONST_V = 0, 1
 CHEM_PERSISTENT, CHEM_PLAIN = 0, 1
 CHEM_FLAG_CHECK_CELLS = 1
@@ -49,6 +51,8 @@ class IntegratorOptions(ctypes.Structure):
         ("newton_max", ctypes.c_int), ("halving_max_depth", ctypes.c_int),
         ("newton_rtol", ctypes.c_double), ("newton_atol_T", ctypes.c_double), ("newton_atol_Y", ctypes.c_double),
         ("probe_attempts", ctypes.c_int), ("reserved_", ctypes.c_int),
+        ("yass_alpha", ctypes.c_double), ("linear_solver", ctypes.c_int), ("krylov_dim", ctypes.c_int),
+        ("krylov_rtol", ctypes.c_double), ("krylov_max_iter", ctypes.c_int), ("krylov_precond", ctypes.c_int),
     ]
 
 

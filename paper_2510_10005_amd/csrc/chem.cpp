@@ -55,25 +55,33 @@ const char* kKernelNames[] = {
     "chem_k_ros2_persistent", "chem_k_ros2_init",       "chem_k_ros2_step",        "chem_k_be_persistent",
     "chem_k_be_init",       "chem_k_be_step",          "chem_k_be_adjoint",       "chem_k_reduce_blocks",
     "chem_k_sched_scan",    "chem_k_sched_scatter",    "chem_k_jac_transpose",    "chem_k_ros2_persistent_rec",
-    "chem_k_ros2_adjoint",  "chem_k_sdirk2_persistent", "chem_k_sdirk4_persistent"};
+    "chem_k_ros2_adjoint",  "chem_k_sdirk2_persistent", "chem_k_sdirk4_persistent",
+    "chem_k_yass_persistent"};
 enum KernelId {
   K_THERMO, K_SOURCE, K_JACOBIAN, K_TPY, K_MASSFRAC, K_TPY_VJP, K_MASSFRAC_VJP, K_FILL_U64,
   K_ROS2_PERSISTENT, K_ROS2_INIT, K_ROS2_STEP, K_BE_PERSISTENT, K_BE_INIT, K_BE_STEP, K_BE_ADJOINT,
   K_REDUCE_BLOCKS, K_SCHED_SCAN, K_SCHED_SCATTER, K_JAC_TRANSPOSE, K_ROS2_PERSISTENT_REC, K_ROS2_ADJOINT,
-  K_SDIRK2_PERSISTENT, K_SDIRK4_PERSISTENT, K_COUNT
+  K_SDIRK2_PERSISTENT, K_SDIRK4_PERSISTENT, K_YASS_PERSISTENT, K_COUNT
 };
 // kernels that only the register-resident form (n <= kDenseLimit) has
 bool dense_only(int k) {
-  return k == K_ROS2_PERSISTENT_REC || k == K_ROS2_ADJOINT || k == K_SDIRK2_PERSISTENT || k == K_SDIRK4_PERSISTENT;
+  return k == K_ROS2_PERSISTENT_REC || k == K_ROS2_ADJOINT || k == K_SDIRK2_PERSISTENT || k == K_SDIRK4_PERSISTENT ||
+         k == K_YASS_PERSISTENT;
 }
 // persistent integration kernel of a method
-bool known_method(int m) { return m == CHEM_BE || m == CHEM_ROS2 || m == CHEM_SDIRK2 || m == CHEM_SDIRK4; }
-bool sdirk(int m) { return m == CHEM_SDIRK2 || m == CHEM_SDIRK4; }
+bool known_method(int m) { return m >= CHEM_BE && m <= CHEM_YASS; }
+// fixed-step methods with only the persistent form and no adjoint tape
+bool persistent_only(int m) { return m == CHEM_SDIRK2 || m == CHEM_SDIRK4 || m == CHEM_YASS; }
+const char* method_name(int m) {
+  static const char* names[] = {"backward Euler", "Rosenbrock", "SDIRK-2", "SDIRK-4", "YASS"};
+  return known_method(m) ? names[m] : "?";
+}
 KernelId persistent_kernel(int method) {
   switch (method) {
     case CHEM_ROS2: return K_ROS2_PERSISTENT;
     case CHEM_SDIRK2: return K_SDIRK2_PERSISTENT;
     case CHEM_SDIRK4: return K_SDIRK4_PERSISTENT;
+    case CHEM_YASS: return K_YASS_PERSISTENT;
     default: return K_BE_PERSISTENT;
   }
 }
@@ -83,6 +91,10 @@ struct DevChemOpts {  // layout mirrors ChemOpts in the generated source
   double dt, rtol, atol, h_min;
   double newton_rtol, newton_atol_T, newton_atol_Y;
   int n_steps, max_steps, newton_max, halving_max_depth, energy, ckpt_every;
+};
+struct DevYassOpts {  // layout mirrors YassOpts in the generated source
+  double alpha, krylov_rtol;
+  int linear_solver, krylov_dim, krylov_max_iter, krylov_precond;
 };
 
 uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull) {
@@ -134,7 +146,7 @@ std::vector<std::string> compile_options(const std::string& arch) {
 // a larger one is split into one program per group, compiled concurrently, because its code is
 // large enough that a single compile is slow.
 constexpr int kGroups = 4;
-const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1, 0, 1, 3, 2, 2};
+const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1, 0, 1, 3, 2, 2, 2};
 
 struct CodeObject {
   std::string code, path;
@@ -271,8 +283,8 @@ struct chem_mech {
   bool wave = false;  // one cell per 64-lane wavefront (blocks of 64)
   DevBuf lnA_default, queue, ws, wst, counters_internal, running, seg, gws, gpart, sched, order, jstage;
   unsigned int* running_host = nullptr;
-  int launch_block[4][2] = {};  // [method][form]
-  int launch_grid[4][2] = {};
+  int launch_block[5][2] = {};  // [method][form]
+  int launch_grid[5][2] = {};
   std::mutex mu;
   ~chem_mech() {
     if (running_host) (void)hipHostFree(running_host);
@@ -333,6 +345,17 @@ DevChemOpts to_dev(const chem_integrator_opts& o, int ckpt_every) {
   return d;
 }
 
+DevYassOpts yass_to_dev(const chem_integrator_opts& o) {
+  DevYassOpts d{};
+  d.alpha = o.yass_alpha;
+  d.krylov_rtol = o.krylov_rtol;
+  d.linear_solver = o.linear_solver;
+  d.krylov_dim = o.krylov_dim;
+  d.krylov_max_iter = o.krylov_max_iter;
+  d.krylov_precond = o.krylov_precond;
+  return d;
+}
+
 chem_err validate_opts(const chem_integrator_opts* o) {
   if (!o) return fail(CHEM_EINVAL, "null options");
   if (!known_method(o->method))
@@ -347,6 +370,15 @@ chem_err validate_opts(const chem_integrator_opts* o) {
   if (o->newton_max < 1 || o->halving_max_depth < 0 || o->halving_max_depth > 30)
     return fail(CHEM_EINVAL, "newton_max >= 1 and 0 <= halving_max_depth <= 30 required");
   if (o->probe_attempts < 0) return fail(CHEM_EINVAL, "probe_attempts must be >= 0");
+  if (o->method == CHEM_YASS) {
+    if (!(o->yass_alpha > 0.0)) return fail(CHEM_EINVAL, "yass_alpha must be positive");
+    if (o->linear_solver != CHEM_LINSOLVE_LU && o->linear_solver != CHEM_LINSOLVE_GMRES)
+      return fail(CHEM_EINVAL, "unknown linear_solver");
+    if (o->krylov_precond != CHEM_PRECOND_NONE && o->krylov_precond != CHEM_PRECOND_JACOBI)
+      return fail(CHEM_EINVAL, "unknown krylov_precond");
+    if (o->krylov_dim < 0 || o->krylov_max_iter < 1 || !(o->krylov_rtol >= 0.0))
+      return fail(CHEM_EINVAL, "krylov_dim >= 0, krylov_max_iter >= 1 and krylov_rtol >= 0 required");
+  }
   return CHEM_OK;
 }
 
@@ -399,6 +431,12 @@ void chem_default_options(chem_integrator_opts* o) {
   o->newton_atol_Y = 1e-14;
   o->probe_attempts = 48;
   o->reserved_ = 0;
+  o->yass_alpha = 0.1;
+  o->linear_solver = CHEM_LINSOLVE_LU;
+  o->krylov_dim = 0;
+  o->krylov_rtol = 1e-12;
+  o->krylov_max_iter = 100;
+  o->krylov_precond = CHEM_PRECOND_JACOBI;
 }
 
 const char* chem_error_string(chem_err e) {
@@ -626,9 +664,10 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
   if (chem_err e = check_cells(M, n, ld)) return e;
   if (chem_err e = validate_opts(opts)) return e;
   if (M->wave) return fail(CHEM_EUNSUPPORTED, kWaveIntegrationOff);
-  if (sdirk(opts->method)) {
-    if (opts->form != CHEM_PERSISTENT) return fail(CHEM_EUNSUPPORTED, "SDIRK schemes run in the persistent form");
-    if (tape) return fail(CHEM_EUNSUPPORTED, "no adjoint tape for the SDIRK schemes");
+  if (persistent_only(opts->method)) {
+    if (opts->form != CHEM_PERSISTENT)
+      return fail(CHEM_EUNSUPPORTED, std::string(method_name(opts->method)) + " runs in the persistent form only");
+    if (tape) return fail(CHEM_EUNSUPPORTED, std::string("no adjoint tape for ") + method_name(opts->method));
   }
   if (tape) {
     if (tape->mech != M) return fail(CHEM_EINVAL, "tape belongs to another mechanism");
@@ -697,7 +736,11 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
     }
     uint64_t* q = M->queue.as<uint64_t>();
     if ((e = fill_u64(M, q, 1, 0, s))) return e;
-    if (sdirk(method)) {
+    if (method == CHEM_YASS) {
+      DevYassOpts yo = yass_to_dev(*opts);
+      void* args[] = {&n, &ld, &y, &la, &o, &yo, &status, &cnt, &q};
+      if ((e = launch(M, k, grid, block, s, args))) return e;
+    } else if (persistent_only(method)) {
       void* args[] = {&n, &ld, &y, &la, &o, &status, &cnt, &q};
       if ((e = launch(M, k, grid, block, s, args))) return e;
     } else if (method == CHEM_ROS2) {
