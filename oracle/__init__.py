@@ -8,7 +8,9 @@ temperature source under constant volume (Section 3, eq.
 temperature_source) or constant pressure (Appendix B), the analytic
 source Jacobian (Section 3.2), backward Euler with Newton (Section 3.2),
 the SDIRK schemes (two and five stages, Appendix A.1/A.2), YASS (Appendix
-A.4) with an LU or Jacobi-preconditioned GMRES solve (Section 3.4) and the
+A.4) with an LU or Jacobi-preconditioned GMRES solve (Section 3.4), the
+CFD coupling (temperature from the energy density by Newton, Section 2.1; the
+linearised species source of the detonation case) and the
 two-stage Rosenbrock scheme (Appendix A.3), plus forward and
 reverse sensitivities of the backward-Euler map and the discrete adjoint
 of the Rosenbrock map along its accepted step sequence.
@@ -38,4 +40,5 @@ from .integrate import (  # noqa: F401
     integrate_sdirk2, integrate_sdirk4, integrate_yass,
 )
 from .linsolve import gmres  # noqa: F401
+from .coupling import T_from_energy, energy_density, openfoam_source  # noqa: F401
 from .sensitivity import be_tangent, be_adjoint, ros2_replay, ros2_adjoint, ros2_adjoint_cell  # noqa: F401
