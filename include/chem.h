@@ -194,6 +194,25 @@ chem_err chem_default_lnA(const chem_mech* mech, double* lnA_host);
 chem_err chem_thermo(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* T,
                      double* cp, double* h, double* s, double* g, void* stream);
 
+/* Temperature from the energy density (Section 2.1, eqs. temperature-nonlinear,
+ * netwons-method-temperature): n_iter Newton iterations (the paper uses 5) of
+ *   T_k = T_{k-1} + (e - e(C, T_{k-1})) / e_T(C, T_{k-1})
+ * with e = rho u = sum_i C_i U_i(T) and e_T = rho c_v = sum_i C_i Cv_i for energy CHEM_CONST_V, or
+ * e = rho h = sum_i C_i H_i(T) and e_T = rho c_p = sum_i C_i Cp_i for CHEM_CONST_P (molar U, H,
+ * Cv, Cp from the NASA-7 fits; Cv = Cp - R).  (The printed update subtracts the quotient; the
+ * Newton equation printed just before it fixes the sign used here.)
+ * C[ns][ld] (kmol/m^3; e.g. the species rows of a state array y + ld), e[ld] (J/m^3) and T0[ld]
+ * (K, the initial guess) in; T[ld] out (T may alias T0).  n_iter >= 1.  No per-cell checks: a
+ * non-positive or non-finite result propagates.  CHEM_EINVAL for null pointers or a bad mode. */
+chem_err chem_T_from_energy(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* C, const double* e,
+                            const double* T0, int energy, int n_iter, double* T, void* stream);
+
+/* Linearised species production term of the CFD coupling (the detonation case's eq. openfom_RR):
+ * R[ns][ld] = W_i (C_i^{n+1} - C_i^n) / dt  [kg/(m^3 s)] from the states y_n and y_np1
+ * ([n][ld] each: T, C) before and after a chemistry step of length dt > 0. */
+chem_err chem_cfd_source(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* y_n, const double* y_np1,
+                         double dt, double* R, void* stream);
+
 /* Source term S(y) (eq. extracted_problem): dydt[n][ld] from y[n][ld]. */
 chem_err chem_source_terms(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* y,
                            const double* lnA, int energy, double* dydt, void* stream);

@@ -30,7 +30,7 @@ EXPORTED = [
     "chem_default_lnA", "chem_thermo", "chem_source_terms", "chem_jacobian", "chem_state_from_TPY",
     "chem_mass_fractions", "chem_state_from_TPY_vjp", "chem_mass_fractions_vjp", "chem_integrate",
     "chem_tape_create", "chem_tape_create_ros2", "chem_tape_free", "chem_integrate_adjoint", "chem_set_launch",
-    "chem_get_launch", "chem_autotune",
+    "chem_get_launch", "chem_autotune", "chem_T_from_energy", "chem_cfd_source",
 ]
 
 
@@ -105,6 +105,8 @@ def load():
     lib.chem_set_launch.argtypes = [_P, _I, _I, _I, _I]
     lib.chem_get_launch.argtypes = [_P, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]
     lib.chem_autotune.argtypes = [_P, _I64, _I64, _P, _P, ctypes.POINTER(IntegratorOptions), _P]
+    lib.chem_T_from_energy.argtypes = [_P, _I64, _I64, _P, _P, _P, _I, _I, _P, _P]
+    lib.chem_cfd_source.argtypes = [_P, _I64, _I64, _P, _P, ctypes.c_double, _P, _P]
     for name in EXPORTED:
         f = getattr(lib, name)
         if f.restype is ctypes.c_int or name not in ("chem_default_options", "chem_free_mechanism",
@@ -178,6 +180,14 @@ class Mechanism:
     def chem_thermo(self, n, ld, T, cp, h, s, g):
         _check(self.lib.chem_thermo(self.handle, n, ld, _ptr(T), _ptr(cp), _ptr(h), _ptr(s), _ptr(g), _stream()),
                "chem_thermo")
+
+    def chem_T_from_energy(self, n, ld, C, e, T0, energy, n_iter, T):
+        _check(self.lib.chem_T_from_energy(self.handle, n, ld, _ptr(C), _ptr(e), _ptr(T0), energy, n_iter, _ptr(T),
+                                           _stream()), "chem_T_from_energy")
+
+    def chem_cfd_source(self, n, ld, y_n, y_np1, dt, R):
+        _check(self.lib.chem_cfd_source(self.handle, n, ld, _ptr(y_n), _ptr(y_np1), dt, _ptr(R), _stream()),
+               "chem_cfd_source")
 
     def chem_source_terms(self, n, ld, y, lnA, energy, dydt):
         _check(self.lib.chem_source_terms(self.handle, n, ld, _ptr(y), _ptr(lnA), energy, _ptr(dydt), _stream()),

@@ -56,12 +56,12 @@ const char* kKernelNames[] = {
     "chem_k_be_init",       "chem_k_be_step",          "chem_k_be_adjoint",       "chem_k_reduce_blocks",
     "chem_k_sched_scan",    "chem_k_sched_scatter",    "chem_k_jac_transpose",    "chem_k_ros2_persistent_rec",
     "chem_k_ros2_adjoint",  "chem_k_sdirk2_persistent", "chem_k_sdirk4_persistent",
-    "chem_k_yass_persistent"};
+    "chem_k_yass_persistent", "chem_k_T_from_energy", "chem_k_cfd_source"};
 enum KernelId {
   K_THERMO, K_SOURCE, K_JACOBIAN, K_TPY, K_MASSFRAC, K_TPY_VJP, K_MASSFRAC_VJP, K_FILL_U64,
   K_ROS2_PERSISTENT, K_ROS2_INIT, K_ROS2_STEP, K_BE_PERSISTENT, K_BE_INIT, K_BE_STEP, K_BE_ADJOINT,
   K_REDUCE_BLOCKS, K_SCHED_SCAN, K_SCHED_SCATTER, K_JAC_TRANSPOSE, K_ROS2_PERSISTENT_REC, K_ROS2_ADJOINT,
-  K_SDIRK2_PERSISTENT, K_SDIRK4_PERSISTENT, K_YASS_PERSISTENT, K_COUNT
+  K_SDIRK2_PERSISTENT, K_SDIRK4_PERSISTENT, K_YASS_PERSISTENT, K_T_FROM_ENERGY, K_CFD_SOURCE, K_COUNT
 };
 // kernels that only the register-resident form (n <= kDenseLimit) has
 bool dense_only(int k) {
@@ -146,7 +146,7 @@ std::vector<std::string> compile_options(const std::string& arch) {
 // a larger one is split into one program per group, compiled concurrently, because its code is
 // large enough that a single compile is slow.
 constexpr int kGroups = 4;
-const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1, 0, 1, 3, 2, 2, 2};
+const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1, 0, 1, 3, 2, 2, 2, 0, 0};
 
 struct CodeObject {
   std::string code, path;
@@ -544,6 +544,26 @@ chem_err chem_thermo(const chem_mech* M, int64_t n, int64_t ld, const double* T,
   if (chem_err e = check_cells(n, ld)) return e;
   void* args[] = {&n, &ld, &T, &cp, &h, &s, &g};
   return launch(M, K_THERMO, blocks_for(n, 256), 256, static_cast<hipStream_t>(stream), args);
+}
+
+chem_err chem_T_from_energy(const chem_mech* M, int64_t n, int64_t ld, const double* C, const double* e,
+                            const double* T0, int energy, int n_iter, double* T, void* stream) {
+  if (!M || !C || !e || !T0 || !T) return fail(CHEM_EINVAL, "null argument");
+  if (chem_err err = check_cells(n, ld)) return err;
+  if (energy != CHEM_CONST_P && energy != CHEM_CONST_V) return fail(CHEM_EINVAL, "unknown energy mode");
+  if (n_iter < 1) return fail(CHEM_EINVAL, "n_iter must be >= 1");
+  void* args[] = {&n, &ld, &C, &e, &T0, &energy, &n_iter, &T};
+  return launch(M, K_T_FROM_ENERGY, blocks_for(n, 256), 256, static_cast<hipStream_t>(stream), args);
+}
+
+chem_err chem_cfd_source(const chem_mech* M, int64_t n, int64_t ld, const double* y_n, const double* y_np1, double dt,
+                         double* R, void* stream) {
+  if (!M || !y_n || !y_np1 || !R) return fail(CHEM_EINVAL, "null argument");
+  if (chem_err err = check_cells(n, ld)) return err;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CHEM_EINVAL, "dt must be positive and finite");
+  double inv_dt = 1.0 / dt;
+  void* args[] = {&n, &ld, &y_n, &y_np1, &inv_dt, &R};
+  return launch(M, K_CFD_SOURCE, blocks_for(n, 256), 256, static_cast<hipStream_t>(stream), args);
 }
 
 chem_err chem_source_terms(const chem_mech* M, int64_t n, int64_t ld, const double* y, const double* lnA, int energy,
