@@ -11,8 +11,8 @@
   solved by full Newton from the initial guess S(y_n).
 * ``integrate_yass``: YASS (Appendix A.4): one linearised backward-Euler solve
   (I - h J(y_n)) dy = h S(y_n) per substep, the substep halved while the decrement is larger
-  than alpha, failure once it would fall below h_min; the solve by LU or by Jacobi-preconditioned
-  GMRES (Section 3.4, ``oracle.linsolve``).
+  than alpha, failure once it would fall below h_min; the solve by LU or by GMRES with Jacobi,
+  Gauss-Seidel or no preconditioning (Section 3.4, ``oracle.linsolve``).
 * ``integrate_ros2``: the two-stage Rosenbrock method of Appendix A.3 with
   gamma = 1 + sqrt(2)/2, alpha = 1/gamma, beta = -2/gamma, m1 = 3/(2 gamma),
   m2 = 1/(2 gamma); the second stage right-hand side is S(y + alpha G1) + (beta/h) G1
@@ -68,7 +68,7 @@ class IntegratorOptions:
     krylov_dim: int = 0             # GMRES restart length (0: the system size)
     krylov_rtol: float = 1e-12      # on the preconditioned residual, relative to |M^-1 b|
     krylov_max_iter: int = 100
-    krylov_jacobi: bool = True      # M = diag(A), else M = I
+    krylov_precond: int = 1         # 0: M = I, 1: Jacobi M = diag(A), 2: Gauss-Seidel M = lower(A)
     krylov_lsq: str = "lstsq"       # GMRES least-squares solve: "lstsq" or "givens"
 
 
@@ -379,7 +379,7 @@ def _linear_solve(A, b, opt):
     """One solve of A x = b (single system): LU with partial pivoting (LAPACK) or GMRES.
     Returns (x, Krylov iterations)."""
     if opt.linear_solver == LINSOLVE_GMRES:
-        x, its, _ = gmres(A, b, opt.krylov_dim, opt.krylov_rtol, opt.krylov_max_iter, opt.krylov_jacobi,
+        x, its, _ = gmres(A, b, opt.krylov_dim, opt.krylov_rtol, opt.krylov_max_iter, opt.krylov_precond,
                           opt.krylov_lsq)
         return x, its
     return np.linalg.solve(A, b), 0

@@ -45,16 +45,34 @@ def _givens_cycle_solve(H, beta, j):
     return y, abs(g[j + 1])
 
 
-def gmres(A, b, m, rtol, max_iter, jacobi=True, lsq="lstsq"):
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_GS = 0, 1, 2
+
+
+def _forward_substitution(L, v):
+    """Solve L w = v for lower-triangular L (row by row)."""
+    w = np.zeros_like(v)
+    for i in range(L.shape[0]):
+        w[i] = (v[i] - L[i, :i] @ w[:i]) / L[i, i]
+    return w
+
+
+def gmres(A, b, m, rtol, max_iter, precond=PRECOND_JACOBI, lsq="lstsq"):
     """Restarted GMRES(m) for one system A x = b ([n, n], [n]).  Returns (x, iterations, converged).
-    m <= 0 means m = n (no restart); ``lsq`` picks the least-squares solve ("lstsq" or "givens")."""
+    m <= 0 means m = n (no restart); ``precond``: PRECOND_NONE (or False), PRECOND_JACOBI (or True),
+    PRECOND_GS; ``lsq`` picks the least-squares solve ("lstsq" or "givens")."""
     A = np.asarray(A, dtype=float)
     b = np.asarray(b, dtype=float)
     n = b.shape[0]
     m = n if m <= 0 else min(m, n)
-    dinv = 1.0 / np.diag(A) if jacobi else np.ones(n)
-    B = dinv[:, None] * A                       # M^-1 A
-    c = dinv * b                                # M^-1 b
+    precond = int(precond)
+    if precond == PRECOND_GS:
+        L = np.tril(A)
+        B = np.stack([_forward_substitution(L, A[:, k]) for k in range(n)], axis=1)   # M^-1 A
+        c = _forward_substitution(L, b)                                               # M^-1 b
+    else:
+        dinv = 1.0 / np.diag(A) if precond == PRECOND_JACOBI else np.ones(n)
+        B = dinv[:, None] * A                       # M^-1 A
+        c = dinv * b                                # M^-1 b
     target = rtol * np.linalg.norm(c)
     x = np.zeros(n)
     its = 0

@@ -5,7 +5,9 @@ GMRES (oracle.linsolve.gmres):
 * its j-th iterate minimises the preconditioned residual over the Krylov space K_j: checked against
   a brute-force least-squares fit over the explicitly formed basis [c, Bc, ..., B^(j-1) c];
 * Jacobi preconditioning solves a diagonal system in one iteration; without it a diagonal system
-  with k distinct entries needs exactly k (the degree of the minimal polynomial);
+  with k distinct entries needs exactly k (the degree of the minimal polynomial); Gauss-Seidel
+  solves a lower-triangular one in one iteration, and its iterates minimise the residual over the
+  Krylov space of M^-1 A (brute force);
 * GMRES(1) is the minimal-residual iteration x <- x + (r.Br / Br.Br) r;
 each with both least-squares solves of the Hessenberg problem (LAPACK lstsq and Givens rotations).
 
@@ -94,6 +96,29 @@ def test_gmres_diagonal_systems(lsq):
     x, its, conv = gmres(A, b, 0, 1e-14, 50, False, lsq)
     assert conv and its == 3
     np.testing.assert_allclose(x, b / d, rtol=1e-13)
+
+
+@pytest.mark.parametrize("lsq", LSQ)
+def test_gmres_gauss_seidel(lsq):
+    """M = lower(A): a lower-triangular system is solved in one iteration (M^-1 A = I); in general
+    the iterates minimise |M^-1 (b - A x)| over the Krylov space of M^-1 A (brute force with M^-1
+    formed by scipy's triangular solve); the full space gives LAPACK's solution."""
+    from scipy.linalg import solve_triangular
+    A, b = _random_system(7, 21, cond_shift=4.0)
+    Lo = np.tril(A)
+    x, its, conv = gmres(Lo, b, 0, 1e-14, 20, oracle.linsolve.PRECOND_GS, lsq)
+    assert conv and its == 1
+    np.testing.assert_allclose(x, np.linalg.solve(Lo, b), rtol=1e-12)
+    Minv_A = solve_triangular(Lo, A, lower=True)
+    c = solve_triangular(Lo, b, lower=True)
+    for j in range(1, 4):
+        x, its, _ = gmres(A, b, 0, 0.0, j, oracle.linsolve.PRECOND_GS, lsq)
+        K = np.stack([np.linalg.matrix_power(Minv_A, i) @ c for i in range(j)], axis=1)
+        x_ref = K @ np.linalg.lstsq(Minv_A @ K, c, rcond=None)[0]
+        assert np.abs(x - x_ref).max() <= 1e-9 * np.abs(x_ref).max()
+    x, its, conv = gmres(A, b, 0, 1e-15, 30, oracle.linsolve.PRECOND_GS, lsq)
+    ref = np.linalg.solve(A, b)
+    assert conv and np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("lsq", LSQ)
