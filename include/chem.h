@@ -63,7 +63,7 @@ enum {
 
 enum { CHEM_BE = 0, CHEM_ROS2 = 1, CHEM_SDIRK2 = 2, CHEM_SDIRK4 = 3, CHEM_YASS = 4 };
 enum { CHEM_LINSOLVE_LU = 0, CHEM_LINSOLVE_GMRES = 1 };
-enum { CHEM_PRECOND_NONE = 0, CHEM_PRECOND_JACOBI = 1 };
+enum { CHEM_PRECOND_NONE = 0, CHEM_PRECOND_JACOBI = 1, CHEM_PRECOND_GAUSS_SEIDEL = 2 };
 enum { CHEM_CONST_P = 0, CHEM_CONST_V = 1 };
 enum { CHEM_PERSISTENT = 0, CHEM_PLAIN = 1 };
 enum { CHEM_FLAG_CHECK_CELLS = 1 };  /* synchronise and return CHEM_ECELLS if a cell failed */
@@ -92,7 +92,9 @@ enum { CHEM_FLAG_CHECK_CELLS = 1 };  /* synchronise and return CHEM_ECELLS if a 
  *                    substep of size h solves the linearised backward-Euler step
  *                    (I - h J(y)) dy = h S(y) once, with LU (linear_solver CHEM_LINSOLVE_LU) or
  *                    restarted GMRES (CHEM_LINSOLVE_GMRES, Section 3.4; left preconditioning by
- *                    M = diag(I - hJ) with CHEM_PRECOND_JACOBI, or none; stop when the Euclidean
+ *                    M = diag(I - hJ) with CHEM_PRECOND_JACOBI, by M = its lower triangle with
+ *                    the diagonal (forward substitution) with CHEM_PRECOND_GAUSS_SEIDEL, or
+ *                    none; stop when the Euclidean
  *                    norm of the preconditioned residual is <= krylov_rtol |M^-1 b|, or after
  *                    krylov_max_iter iterations; restart length krylov_dim, 0 = system size).
  *                    The substep is accepted when dy is finite, T stays > 0 and
@@ -140,7 +142,7 @@ typedef struct {
   int krylov_dim;       /* GMRES restart length, 0 = the size of the solved system */
   double krylov_rtol;   /* GMRES stop: preconditioned residual <= krylov_rtol |M^-1 b| */
   int krylov_max_iter;  /* GMRES iterations per solve, over all restarts */
-  int krylov_precond;   /* CHEM_PRECOND_JACOBI or CHEM_PRECOND_NONE */
+  int krylov_precond;   /* CHEM_PRECOND_JACOBI, CHEM_PRECOND_GAUSS_SEIDEL or CHEM_PRECOND_NONE */
 } chem_integrator_opts;
 
 /* Defaults: BE, const-p, persistent, dt 1e-7, n_steps 0, max_steps 100000, rtol 1e-6, atol 1e-10,

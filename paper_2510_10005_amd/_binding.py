@@ -17,7 +17,7 @@ _LIBPATH = os.path.join(_PKG, "libchem.so")
 CHEM_OK = 0
 CHEM_BE, CHEM_ROS2, CHEM_SDIRK2, CHEM_SDIRK4, CHEM_YASS = 0, 1, 2, 3, 4
 CHEM_LINSOLVE_LU, CHEM_LINSOLVE_GMRES = 0, 1
-CHEM_PRECOND_NONE, CHEM_PRECOND_JACOBI = 0, 1
+CHEM_PRECOND_NONE, CHEM_PRECOND_JACOBI, CHEM_PRECOND_GAUSS_SEIDEL = 0, 1, 2
 CHEM_CONST_P, CHEM_CONST_V = 0, 1
 CHEM_PERSISTENT, CHEM_PLAIN = 0, 1
 CHEM_FLAG_CHECK_CELLS = 1

@@ -374,7 +374,8 @@ chem_err validate_opts(const chem_integrator_opts* o) {
     if (!(o->yass_alpha > 0.0)) return fail(CHEM_EINVAL, "yass_alpha must be positive");
     if (o->linear_solver != CHEM_LINSOLVE_LU && o->linear_solver != CHEM_LINSOLVE_GMRES)
       return fail(CHEM_EINVAL, "unknown linear_solver");
-    if (o->krylov_precond != CHEM_PRECOND_NONE && o->krylov_precond != CHEM_PRECOND_JACOBI)
+    if (o->krylov_precond != CHEM_PRECOND_NONE && o->krylov_precond != CHEM_PRECOND_JACOBI &&
+        o->krylov_precond != CHEM_PRECOND_GAUSS_SEIDEL)
       return fail(CHEM_EINVAL, "unknown krylov_precond");
     if (o->krylov_dim < 0 || o->krylov_max_iter < 1 || !(o->krylov_rtol >= 0.0))
       return fail(CHEM_EINVAL, "krylov_dim >= 0, krylov_max_iter >= 1 and krylov_rtol >= 0 required");

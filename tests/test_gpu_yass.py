@@ -25,7 +25,8 @@ under ulp perturbations.)
 
 Cases: the backward-Euler workload's states at the paper's YASS step (1e-7 s, Table 5) and at
 2 x 1e-6 s (substep halving active) in both energy modes, a tighter alpha, GMRES with Jacobi
-preconditioning (both energy modes, a tighter alpha, restarted GMRES(4)) and without, the Rosenbrock
+preconditioning (both energy modes, a tighter alpha, restarted GMRES(4)), with Gauss-Seidel
+preconditioning (both energy modes) and without, the Rosenbrock
 workload's hot states, the h_min failure and the attempt budget, argument errors, and sampled
 cells of the 1024-cell workload over its 2e-5 s at the paper's step with the autotuned launch.
 """
@@ -54,12 +55,8 @@ def mechs(request):
 
 
 def _gpu_opts(kw):
-    """Oracle option names -> library option names."""
-    from paper_2510_10005_amd import CHEM_PRECOND_JACOBI, CHEM_PRECOND_NONE
-    out = dict(kw)
-    if "krylov_jacobi" in out:
-        out["krylov_precond"] = CHEM_PRECOND_JACOBI if out.pop("krylov_jacobi") else CHEM_PRECOND_NONE
-    return out
+    """Oracle options -> library options (the same names; krylov_lsq is the oracle's alone)."""
+    return {k: v for k, v in kw.items() if k != "krylov_lsq"}
 
 
 def _run(gm, y0, dt, n_steps, ld=None, **kw):
@@ -124,7 +121,9 @@ CASES = {
     "gmres_jacobi_cv": ("be_small", 150, 2e-6, 2, 1, dict(linear_solver=1)),
     "gmres_jacobi_tight_alpha": ("be_small", 150, 1e-6, 1, 0, dict(linear_solver=1, yass_alpha=0.01)),
     "gmres_restart4": ("be_small", 150, 2e-6, 2, 0, dict(linear_solver=1, krylov_dim=4)),
-    "gmres_no_precond": ("be_small", 150, 2e-6, 2, 0, dict(linear_solver=1, krylov_jacobi=False)),
+    "gmres_no_precond": ("be_small", 150, 2e-6, 2, 0, dict(linear_solver=1, krylov_precond=0)),
+    "gmres_gauss_seidel": ("be_small", 150, 2e-6, 2, 0, dict(linear_solver=1, krylov_precond=2)),
+    "gmres_gauss_seidel_cv": ("be_small", 150, 2e-6, 2, 1, dict(linear_solver=1, krylov_precond=2)),
     "hot_states": ("ros2_1m", 150, 1e-7, 5, 0, {}),
 }
 
@@ -176,7 +175,7 @@ def test_yass_argument_errors(mechs):
     with pytest.raises(ChemError, match="no adjoint tape"):
         gm.chem_integrate(8, 8, y, None, default_options(method=CHEM_YASS, dt=1e-8), Tape(gm, 8, 2), st, None)
     for kw, msg in ((dict(yass_alpha=0.0), "yass_alpha"), (dict(linear_solver=7), "linear_solver"),
-                    (dict(krylov_precond=3), "krylov_precond"), (dict(krylov_max_iter=0), "krylov_max_iter")):
+                    (dict(krylov_precond=5), "krylov_precond"), (dict(krylov_max_iter=0), "krylov_max_iter")):
         with pytest.raises(ChemError, match=msg):
             gm.chem_integrate(8, 8, y, None, default_options(method=CHEM_YASS, dt=1e-8, **kw), None, st, None)
 
