@@ -10,7 +10,8 @@ Definitions followed (all in SI-kmol units):
 * k_A = exp(ln A + b ln T - theta / T)                         (Arrhenius, log form)
 * third body: k_f = [M] k_A, [M] = sum_i alpha_ij C_i             (eqs. third_body, TB_optimization)
 * falloff: k_f = k_inf * P_r / (1 + P_r) * F, P_r = k_0 [M] / k_inf  (eq. falloff-reaction)
-* Troe F from F_cent, c, n, f1 (eq. f_and_fcent); Lindemann F = 1
+* Troe F from F_cent, c, n, f1 (eq. f_and_fcent); SRI F = d [a exp(-b/T) + exp(-T/c)]^X T^e with
+  X = 1/(1 + (log10 P_r)^2) (the SRI form Section 2.2 lists beside Troe); Lindemann F = 1
 * K_j = exp(-sum_i nu_ij g_i/RT) (p_ref / RT)^(sum_i nu_ij),  k_r = k_f / K_j  (eqs. reverse_rate,
   equilibrium-constant)
 * q_j = k_f prod C^nu_f - k_r prod C^nu_r; omega_i = sum_j nu_ij q_j
@@ -96,6 +97,29 @@ def _troe(rx, T, Pr, magnitude=False):
     return F, dlogF_dlPr, dlogF_dL * dL_dT, mag
 
 
+def _sri(rx, T, Pr):
+    """SRI broadening F = d [a exp(-b/T) + exp(-T/c)]^X T^e, X = 1/(1 + (log10 P_r)^2).
+
+    Returns (F, dlog10F/dlog10Pr, dlog10F/dT at fixed Pr, term-wise size of the T derivative).
+    """
+    a, b, c, d, e = rx.sri
+    ea = np.exp(-b / T)
+    ec = np.exp(-T / c)
+    B = a * ea + ec
+    B = np.where(np.real(B) > 1e-300, B, 1e-300)
+    Prc = np.where(np.real(Pr) > 1e-300, Pr, 1e-300)
+    lPr = np.log(Prc) / LN10
+    X = 1.0 / (1.0 + lPr * lPr)
+    log10F = np.log(d) / LN10 + X * np.log(B) / LN10 + e * np.log(T) / LN10
+    F = np.exp(LN10 * log10F)
+    dlogF_dlPr = (np.log(B) / LN10) * (-2.0 * lPr * X * X)
+    dB = a * b / (T * T) * ea - ec / c
+    dlogF_dT = (X * dB / B + e / T) / LN10
+    dB_mag = np.abs(a) * b / np.abs(T * T) * np.abs(ea) + np.abs(ec) / c
+    mag = (np.abs(X) * dB_mag / np.abs(B) + abs(e) / np.abs(T)) / LN10
+    return F, dlogF_dlPr, dlogF_dT, mag
+
+
 def _forward_rate(mech, rx, j, T, lnT, invT, C, lnA):
     """k_f and the pieces needed by the Jacobian.
 
@@ -118,6 +142,8 @@ def _forward_rate(mech, rx, j, T, lnT, invT, C, lnA):
     dlnPr_dT_mag = (abs(rx.b0 - rx.b) + abs(rx.theta0 - rx.theta) * np.abs(invT)) * np.abs(invT)
     if rx.troe is not None:
         F, dlF_dlPr, dlF_dT, dlF_dT_mag = _troe(rx, T, Pr, magnitude=True)
+    elif rx.sri is not None:
+        F, dlF_dlPr, dlF_dT, dlF_dT_mag = _sri(rx, T, Pr)
     else:
         F, dlF_dlPr, dlF_dT, dlF_dT_mag = 1.0, 0.0, 0.0, 0.0
     kf = kinf * Pr / (1.0 + Pr) * F
@@ -187,15 +213,18 @@ def source_terms(mech, y, lnA=None, energy=CONST_P):
 
 
 def source_sum_scale(mech, y, lnA=None, energy=CONST_P):
-    """Magnitude of the sums that form S: sum_j |nu_ij q_j| per species and the matching T term.
+    """Magnitude of the sums that form S: sum_j |nu_ij| (|R_f,j| + |R_r,j|) per species and the
+    matching T term.
 
     Used to express floating-point tolerances relative to the size of the terms that
-    are summed (the bound on summation error), not to the possibly cancelled result.
+    are summed (the bound on summation error), not to the possibly cancelled result.  Each
+    q_j = R_f - R_r is itself such a sum: near partial equilibrium R_f and R_r nearly cancel, so
+    the scale takes both rates, not |q_j|.
     """
     y, T, C, lnA = _prepare(mech, y, lnA)
-    q, _, _, th = rates_of_progress(mech, y, lnA)
+    _, Rf, Rr, th = rates_of_progress(mech, y, lnA)
     cp_R, h_RT = th[0], th[1]
-    mag = np.abs(q) @ np.abs(mech.nu.T)
+    mag = (np.abs(Rf) + np.abs(Rr)) @ np.abs(mech.nu.T)
     hw, cw = _temperature_weights(h_RT, cp_R, energy)
     D = (C * cw).sum(axis=1)
     magT = np.abs(T) * (np.abs(hw) * mag).sum(axis=1) / np.abs(D)

@@ -1,7 +1,7 @@
 """Mechanism file reader for the oracle (its own parser; the HIP library has another).
 
 The file is Cantera-like JSON: species with NASA-7 data, reactions of type
-``elementary``, ``three-body`` or ``falloff`` (Troe or Lindemann), rate
+``elementary``, ``three-body`` or ``falloff`` (Troe, SRI or Lindemann), rate
 constants {A, b, Ea} in SI-kmol units with Ea in J/kmol (the paper's worked
 example H + O2 <=> O + OH uses A = 1.0399e11, Ea = 6.405704e7, Section 4.3).
 """
@@ -30,6 +30,7 @@ class Reaction:
     b0: float = 0.0
     theta0: float = 0.0
     troe: tuple | None = None  # (alpha, T3, T1, T2 or None)
+    sri: tuple | None = None   # (a, b, c, d, e) of the SRI broadening
     eff: np.ndarray | None = None  # third-body efficiencies alpha_ij (dense, default 1)
 
 
@@ -70,6 +71,10 @@ class Mechanism:
                     t = r["Troe"]
                     rx.troe = (float(t["A"]), float(t["T3"]), float(t["T1"]),
                                float(t["T2"]) if "T2" in t else None)
+                elif "SRI" in r:
+                    t = r["SRI"]
+                    rx.sri = (float(t["A"]), float(t["B"]), float(t["C"]), float(t.get("D", 1.0)),
+                              float(t.get("E", 0.0)))
             else:
                 k = r["rate-constant"]
                 rx.lnA, rx.b, rx.theta = math.log(k["A"]), float(k["b"]), float(k["Ea"]) / R

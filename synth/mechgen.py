@@ -68,6 +68,7 @@ class MechConfig:
     inert: tuple          # inert collider species (appear in no reaction)
     reference: tuple      # reference diatomics forced into the species list
     isomers: bool = False
+    broadening: str = "troe"   # falloff broadening: "troe" or "sri"
 
 
 MECH_CONFIGS = {
@@ -83,6 +84,9 @@ MECH_CONFIGS = {
     # tiny mechanisms for unit tests
     "tiny_5_6": MechConfig("tiny_5_6", 1010, ("H", "O"), 5, 6, 1, 1, 3, (), ("H2", "O2")),
     "tiny_8_14": MechConfig("tiny_8_14", 1011, ("H", "O", "N"), 8, 14, 2, 2, 4, ("N2",), ("H2", "O2")),
+    # 12 species from {H, O, N}; 30 reactions: 6 falloff with SRI broadening, 4 third-body
+    "sri_12_30": MechConfig("sri_12_30", 1012, ("H", "O", "N"), 12, 30, 4, 6, 4, ("N2",), ("H2", "O2"),
+                            broadening="sri"),
 }
 
 
@@ -448,10 +452,17 @@ def generate_mechanism(name: str) -> dict:
                 rx["high-P-rate-constant"] = _arrhenius(rng, sum(reac.values()))
                 rx["low-P-rate-constant"] = _arrhenius(rng, sum(reac.values()) + 1)
                 lo, hi = math.log(50.0), math.log(1.0e4)
-                rx["Troe"] = {"A": float(rng.uniform(0.4, 0.9)),
-                              "T3": float(math.exp(rng.uniform(lo, hi))),
-                              "T1": float(math.exp(rng.uniform(lo, hi))),
-                              "T2": float(math.exp(rng.uniform(lo, hi)))}
+                if cfg.broadening == "sri":
+                    rx["SRI"] = {"A": float(rng.uniform(0.3, 2.0)),
+                                 "B": float(math.exp(rng.uniform(math.log(50.0), math.log(1.0e3)))),
+                                 "C": float(math.exp(rng.uniform(math.log(200.0), math.log(3.0e3)))),
+                                 "D": float(rng.uniform(0.8, 1.2)),
+                                 "E": float(rng.uniform(-0.3, 0.3))}
+                else:
+                    rx["Troe"] = {"A": float(rng.uniform(0.4, 0.9)),
+                                  "T3": float(math.exp(rng.uniform(lo, hi))),
+                                  "T1": float(math.exp(rng.uniform(lo, hi))),
+                                  "T2": float(math.exp(rng.uniform(lo, hi)))}
         rx_out.append(rx)
     return {
         "description": f"synthetic mechanism {name}: {len(species)} species, {len(rx_out)} reactions",

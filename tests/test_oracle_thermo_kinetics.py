@@ -109,7 +109,7 @@ def test_mass_and_element_conservation(name):
     assert np.all(om[:, m.inert] == 0.0)
 
 
-@pytest.mark.parametrize("name", ["tiny_8_14", "h2like_10_27", "ch4like_53_325"])
+@pytest.mark.parametrize("name", ["tiny_8_14", "h2like_10_27", "sri_12_30", "ch4like_53_325"])
 def test_detailed_balance_at_gibbs_equilibrium(name):
     """mu_i = g_i + RT ln(C_i RT / p_ref) = sum_e lambda_e E_ei makes every q_j vanish."""
     from synth import mechanism_file
