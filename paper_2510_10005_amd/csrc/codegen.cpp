@@ -96,6 +96,14 @@ static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool ja
     os << "    const " << ty << " kf = exp(lnk);\n";
   } else if (r.kind == RxKind::ThirdBody) {
     os << "    const " << ty << " kf = M*exp(lnk);\n";
+  } else if (r.sri) {
+    const double db = r.k0.b - r.k.b, dth = r.k0.theta - r.k.theta, dlnA = r.k0.lnA - r.k.lnA;
+    os << "    " << ty << " kf, dlnkf_dT_fo, dlnkf_dM_fo;\n";
+    os << "    chem_falloff_sri<" << (vjp ? "true" : (jac ? "JAC" : "false")) << ">(lnk, " << num(dlnA) << " + "
+       << num(db) << "*lnT - " << num(dth) << "*invT, M, T, invT, lnT, " << num(r.k.b) << ", " << num(r.k.theta)
+       << ", " << num(db) << ", " << num(dth) << ", " << num(r.sri_a) << ", " << num(r.sri_b) << ", "
+       << num(1.0 / r.sri_c) << ", " << num(std::log(r.sri_d)) << ", " << num(r.sri_e)
+       << ", kf, dlnkf_dT_fo, dlnkf_dM_fo);\n";
   } else {
     const double db = r.k0.b - r.k.b, dth = r.k0.theta - r.k.theta, dlnA = r.k0.lnA - r.k.lnA;
     os << "    " << ty << " kf, dlnkf_dT_fo, dlnkf_dM_fo;\n";
@@ -254,6 +262,8 @@ static void emit_array(std::ostringstream& os, const char* type, const char* nam
 
 static void emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
   const int ns = m.ns(), nr = m.nr();
+  for (const Reaction& r : m.reactions)
+    if (r.sri) throw std::runtime_error("SRI falloff is supported for mechanisms of at most 24 state components");
   auto kind_of = [&](const Reaction& r) {
     if (r.kind == RxKind::Elementary) return 0;
     if (r.kind == RxKind::ThirdBody) return 1;

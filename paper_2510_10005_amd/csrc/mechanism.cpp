@@ -101,6 +101,15 @@ Mechanism parse_mechanism(const std::string& text) {
         rx.troe_has_T2 = t.has("T2");
         if (rx.troe_has_T2) rx.troe_T2 = t["T2"].number();
         if (!(rx.troe_T3 > 0.0) || !(rx.troe_T1 > 0.0)) throw std::runtime_error("Troe T3 and T1 must be positive");
+      } else if (r.has("SRI")) {
+        const auto& t = r["SRI"];
+        rx.sri = true;
+        rx.sri_a = t["A"].number();
+        rx.sri_b = t["B"].number();
+        rx.sri_c = t["C"].number();
+        rx.sri_d = t.has("D") ? t["D"].number() : 1.0;
+        rx.sri_e = t.has("E") ? t["E"].number() : 0.0;
+        if (!(rx.sri_c > 0.0) || !(rx.sri_d > 0.0)) throw std::runtime_error("SRI C and D must be positive");
       }
     } else {
       rx.k = read_arrhenius(r["rate-constant"]);

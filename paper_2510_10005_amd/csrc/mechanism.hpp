@@ -27,6 +27,8 @@ struct Reaction {
   bool troe = false;
   double troe_alpha = 0.0, troe_T3 = 0.0, troe_T1 = 0.0, troe_T2 = 0.0;
   bool troe_has_T2 = false;
+  bool sri = false;   // SRI broadening F = d [a exp(-b/T) + exp(-T/c)]^X T^e
+  double sri_a = 0.0, sri_b = 0.0, sri_c = 1.0, sri_d = 1.0, sri_e = 0.0;
   double default_eff = 1.0;
   std::vector<std::pair<int, double>> eff;      // species with alpha != default
   std::string equation;
