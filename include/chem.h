@@ -4,7 +4,7 @@
  * The library evaluates, for every CFD cell independently, the chemical state y = (T, C_1..C_ns)
  * of the ChemGen paper (arXiv 2510.10005, Section 3, eq. extracted_problem): NASA-7 species
  * thermodynamics (Section 2.1, Table 1), the source term S(y) = (omega_T, omega_1..omega_ns) with
- * Arrhenius, third-body and Troe/Lindemann falloff rates and reverse rates from equilibrium
+ * Arrhenius, third-body and Troe/SRI/Lindemann falloff rates and reverse rates from equilibrium
  * constants (Section 2.2), its analytic Jacobian (Section 3.2), and the implicit integration of
  * dy/dt = S(y) over one operator-split step (backward Euler with Newton, Section 3.2; two-stage
  * Rosenbrock, Appendix A.3), plus the discrete adjoints of both integrations.
@@ -158,7 +158,8 @@ const char* chem_last_error_message(void);
 
 /*
  * Load a mechanism file (Cantera-like JSON: species with NASA-7 data; reactions of type
- * elementary, three-body or falloff with Troe or Lindemann broadening; A, b, Ea in SI-kmol with
+ * elementary, three-body or falloff with Troe, SRI (Section 2.2; n <= 24 only) or Lindemann
+ * broadening; A, b, Ea in SI-kmol with
  * Ea in J/kmol -- the units of the paper's worked example, Section 4.3), validate it, generate
  * HIP source specialised to it (the code-generation step of Section 4.3) and compile it for the
  * current device's architecture with hipRTC.  Compiled code objects are cached in cache_dir (or
