@@ -12,6 +12,7 @@ Definitions followed (all in SI-kmol units):
 * falloff: k_f = k_inf * P_r / (1 + P_r) * F, P_r = k_0 [M] / k_inf  (eq. falloff-reaction)
 * Troe F from F_cent, c, n, f1 (eq. f_and_fcent); SRI F = d [a exp(-b/T) + exp(-T/c)]^X T^e with
   X = 1/(1 + (log10 P_r)^2) (the SRI form Section 2.2 lists beside Troe); Lindemann F = 1
+* P-log: ln k interpolated linearly in ln p between tabulated Arrhenius sets, p = R T sum C
 * K_j = exp(-sum_i nu_ij g_i/RT) (p_ref / RT)^(sum_i nu_ij),  k_r = k_f / K_j  (eqs. reverse_rate,
   equilibrium-constant)
 * q_j = k_f prod C^nu_f - k_r prod C^nu_r; omega_i = sum_j nu_ij q_j
@@ -120,12 +121,49 @@ def _sri(rx, T, Pr):
     return F, dlogF_dlPr, dlogF_dT, mag
 
 
+def _plog_rate(rx, j, T, lnT, invT, C, lnA):
+    """P-log (Section 2.2, other pressure-dependent forms): ln k is interpolated linearly in ln p
+    between the Arrhenius sets of the two tabulated pressures around p = R T sum_i C_i, and held
+    at the end sets outside the table.  Every set carries the same ln A shift as the reaction's
+    parameter lnA[j] (which is ln A of the lowest-pressure set).
+    Returns (kf, dlnkf_dT, M = sum C, dlnkf_dM, |dlnkf_dT| term-wise, |dlnkf_dM|)."""
+    M = C.sum(axis=1)
+    lnp = np.log(R * T * M)
+    sets = rx.plog
+    lnk = [lnA[j] + (lA - rx.lnA) + b * lnT - th * invT for _, lA, b, th in sets]
+    dk = [(b + th * invT) * invT for _, _, b, th in sets]
+    dk_mag = [(abs(b) + abs(th) * np.abs(invT)) * np.abs(invT) for _, _, b, th in sets]
+    lr = np.real(lnp)
+    out_k = lnk[0] + 0.0 * lnp
+    out_dT = dk[0] + 0.0 * lnp
+    out_dp = 0.0 * lnp
+    out_mag = dk_mag[0] + 0.0 * lr
+    for i in range(len(sets) - 1):
+        l0, l1 = sets[i][0], sets[i + 1][0]
+        inside = (lr > l0) & (lr <= l1)
+        w = (lnp - l0) / (l1 - l0)
+        out_k = np.where(inside, lnk[i] + w * (lnk[i + 1] - lnk[i]), out_k)
+        out_dT = np.where(inside, (1.0 - w) * dk[i] + w * dk[i + 1], out_dT)
+        out_dp = np.where(inside, (lnk[i + 1] - lnk[i]) / (l1 - l0), out_dp)
+        out_mag = np.where(inside, np.abs(1.0 - w) * dk_mag[i] + np.abs(w) * dk_mag[i + 1], out_mag)
+    above = lr > sets[-1][0]
+    out_k = np.where(above, lnk[-1], out_k)
+    out_dT = np.where(above, dk[-1], out_dT)
+    out_mag = np.where(above, dk_mag[-1], out_mag)
+    # d ln p / dT = 1/T and d ln p / dC_k = 1/sum C at fixed C and T
+    dlnkf_dT = out_dT + out_dp * invT
+    mag_T = out_mag + np.abs(out_dp) * np.abs(invT)
+    return np.exp(out_k), dlnkf_dT, M, out_dp / M, mag_T, np.abs(out_dp) / np.abs(M)
+
+
 def _forward_rate(mech, rx, j, T, lnT, invT, C, lnA):
     """k_f and the pieces needed by the Jacobian.
 
     Returns (kf, dlnkf_dT, M, dlnkf_dM, |dlnkf_dT| term-wise, |dlnkf_dM| term-wise);
     M is None for elementary reactions.
     """
+    if rx.kind == "plog":
+        return _plog_rate(rx, j, T, lnT, invT, C, lnA)
     lnk = lnA[j] + rx.b * lnT - rx.theta * invT
     dlnk_dT = (rx.b + rx.theta * invT) * invT
     dlnk_dT_mag = (abs(rx.b) + abs(rx.theta) * np.abs(invT)) * np.abs(invT)

@@ -1,7 +1,8 @@
 """Mechanism file reader for the oracle (its own parser; the HIP library has another).
 
 The file is Cantera-like JSON: species with NASA-7 data, reactions of type
-``elementary``, ``three-body`` or ``falloff`` (Troe, SRI or Lindemann), rate
+``elementary``, ``three-body``, ``falloff`` (Troe, SRI or Lindemann) or
+``pressure-dependent-Arrhenius`` (P-log: Arrhenius sets at given pressures), rate
 constants {A, b, Ea} in SI-kmol units with Ea in J/kmol (the paper's worked
 example H + O2 <=> O + OH uses A = 1.0399e11, Ea = 6.405704e7, Section 4.3).
 """
@@ -31,6 +32,7 @@ class Reaction:
     theta0: float = 0.0
     troe: tuple | None = None  # (alpha, T3, T1, T2 or None)
     sri: tuple | None = None   # (a, b, c, d, e) of the SRI broadening
+    plog: list | None = None   # P-log: [(ln p_i, ln A_i, b_i, theta_i)] sorted by pressure
     eff: np.ndarray | None = None  # third-body efficiencies alpha_ij (dense, default 1)
 
 
@@ -75,9 +77,17 @@ class Mechanism:
                     t = r["SRI"]
                     rx.sri = (float(t["A"]), float(t["B"]), float(t["C"]), float(t.get("D", 1.0)),
                               float(t.get("E", 0.0)))
+            elif kind == "pressure-dependent-Arrhenius":
+                sets = sorted((math.log(float(k["P"])), math.log(k["A"]), float(k["b"]), float(k["Ea"]) / R)
+                              for k in r["rate-constants"])
+                rx.kind = kind = "plog"
+                rx.plog = sets
+                rx.lnA, rx.b, rx.theta = sets[0][1], sets[0][2], sets[0][3]
             else:
                 k = r["rate-constant"]
                 rx.lnA, rx.b, rx.theta = math.log(k["A"]), float(k["b"]), float(k["Ea"]) / R
+            if kind == "plog":
+                rx.eff = np.ones(self.ns)             # p = R T sum_i C_i: every species counts once
             if kind in ("three-body", "falloff"):
                 eff = np.full(self.ns, float(r.get("default-efficiency", 1.0)))
                 for k, v in r.get("efficiencies", {}).items():

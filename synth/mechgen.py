@@ -69,6 +69,7 @@ class MechConfig:
     reference: tuple      # reference diatomics forced into the species list
     isomers: bool = False
     broadening: str = "troe"   # falloff broadening: "troe" or "sri"
+    n_plog: int = 0            # elementary reactions rewritten as P-log tables (the first ones drawn)
 
 
 MECH_CONFIGS = {
@@ -87,7 +88,12 @@ MECH_CONFIGS = {
     # 12 species from {H, O, N}; 30 reactions: 6 falloff with SRI broadening, 4 third-body
     "sri_12_30": MechConfig("sri_12_30", 1012, ("H", "O", "N"), 12, 30, 4, 6, 4, ("N2",), ("H2", "O2"),
                             broadening="sri"),
+    # 12 species from {H, O, N}; 30 reactions: 8 P-log (3 pressures), 4 third-body, 2 Troe falloff
+    "plog_12_30": MechConfig("plog_12_30", 1013, ("H", "O", "N"), 12, 30, 4, 2, 4, ("N2",), ("H2", "O2"),
+                             n_plog=8),
 }
+
+PLOG_PRESSURES = (1.0e4, 1.0e5, 1.0e6)   # Pa: the table straddles the workloads' ~1 atm
 
 
 # --------------------------------------------------------------------------- species
@@ -423,6 +429,7 @@ def generate_mechanism(name: str) -> dict:
         raise RuntimeError(f"could not draw mechanism {name}")
     names = [sp.name for sp in species]
     rx_out = []
+    n_plog_left = cfg.n_plog
     for a, b, kind in reactions:
         dH = sum(species[i].dh_f for i in b) - sum(species[i].dh_f for i in a)
         if dH > 0.0:  # write every reaction in its exothermic direction
@@ -434,7 +441,18 @@ def generate_mechanism(name: str) -> dict:
             return " + ".join(f"{c} {s}" if c > 1 else s for s, c in d.items())
 
         rx = {"reactants": reac, "products": prod, "reversible": True}
-        if kind == "elementary":
+        if kind == "elementary" and n_plog_left > 0:
+            n_plog_left -= 1
+            rx["type"] = "pressure-dependent-Arrhenius"
+            rx["equation"] = f"{side(reac)} <=> {side(prod)}"
+            base = _arrhenius(rng, sum(reac.values()))
+            rx["rate-constants"] = []
+            for P in PLOG_PRESSURES:
+                db = float(rng.uniform(-0.3, 0.3))     # A compensated so that k(1000 K) moves by e^U[-1.5, 1.5]
+                rx["rate-constants"].append(
+                    {"P": P, "A": base["A"] * math.exp(float(rng.uniform(-1.5, 1.5)) - db * math.log(T_REF_RATE)),
+                     "b": base["b"] + db, "Ea": base["Ea"] * float(rng.uniform(0.9, 1.1))})
+        elif kind == "elementary":
             rx["type"] = "elementary"
             rx["equation"] = f"{side(reac)} <=> {side(prod)}"
             rx["rate-constant"] = _arrhenius(rng, sum(reac.values()))
