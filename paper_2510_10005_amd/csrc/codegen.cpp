@@ -96,6 +96,35 @@ static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool ja
     os << "    const " << ty << " kf = exp(lnk);\n";
   } else if (r.kind == RxKind::ThirdBody) {
     os << "    const " << ty << " kf = M*exp(lnk);\n";
+  } else if (r.kind == RxKind::Plog) {
+    // ln k linear in ln p between the tabulated sets around p = R T sum C, the end sets outside;
+    // set i relative to the first: ln k_i = lnk + (lnA_i - lnA_0) + (b_i - b_0) ln T - (th_i - th_0)/T
+    const auto& P = r.plog;
+    const int np = static_cast<int>(P.size());
+    os << "    " << ty << " kf, dlnkf_dT_fo, dlnkf_dM_fo;\n    {\n";
+    os << "      const " << ty << " lnp = log(CHEM_R*T*M);\n";
+    os << "      " << ty << " lk, dkT, dkp;\n";
+    auto set_lnk = [&](int i) {
+      const Arrhenius& k = P[i].second;
+      return std::string("(lnk + ") + num(k.lnA - P[0].second.lnA) + " + " + num(k.b - P[0].second.b) + "*lnT - " +
+             num(k.theta - P[0].second.theta) + "*invT)";
+    };
+    auto set_dT = [&](int i) {
+      const Arrhenius& k = P[i].second;
+      return std::string("((") + num(k.b) + " + " + num(k.theta) + "*invT)*invT)";
+    };
+    os << "      if (chem_val(lnp) <= " << num(P[0].first) << ") { lk = " << set_lnk(0) << "; dkT = " << set_dT(0)
+       << "; dkp = 0.0; }\n";
+    for (int i = 0; i + 1 < np; ++i) {
+      const double inv = 1.0 / (P[i + 1].first - P[i].first);
+      os << "      else if (chem_val(lnp) <= " << num(P[i + 1].first) << ") {\n";
+      os << "        const " << ty << " k0 = " << set_lnk(i) << ", k1 = " << set_lnk(i + 1) << ";\n";
+      os << "        const " << ty << " w = (lnp - " << num(P[i].first) << ")*" << num(inv) << ";\n";
+      os << "        lk = k0 + w*(k1 - k0);\n        dkp = (k1 - k0)*" << num(inv) << ";\n";
+      os << "        dkT = (1.0 - w)*" << set_dT(i) << " + w*" << set_dT(i + 1) << ";\n      }\n";
+    }
+    os << "      else { lk = " << set_lnk(np - 1) << "; dkT = " << set_dT(np - 1) << "; dkp = 0.0; }\n";
+    os << "      kf = exp(lk);\n      dlnkf_dT_fo = dkT + dkp*invT;\n      dlnkf_dM_fo = dkp/M;\n    }\n";
   } else if (r.sri) {
     const double db = r.k0.b - r.k.b, dth = r.k0.theta - r.k.theta, dlnA = r.k0.lnA - r.k.lnA;
     os << "    " << ty << " kf, dlnkf_dT_fo, dlnkf_dM_fo;\n";
@@ -162,7 +191,7 @@ static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool ja
       os << "    w[" << p.first << "] = fma(" << num(static_cast<double>(p.second)) << ", q, w[" << p.first << "]);\n";
   }
   os << (vjp ? "    {\n" : "    if (JAC) {\n");
-  if (r.kind == RxKind::Falloff) {
+  if (r.kind == RxKind::Falloff || r.kind == RxKind::Plog) {
     os << "      const " << ty << " dlnkf_dT = dlnkf_dT_fo;\n";
   } else {
     os << "      const " << ty << " dlnkf_dT = (" << num(r.k.b) << " + " << num(r.k.theta) << "*invT)*invT;\n";
@@ -262,8 +291,11 @@ static void emit_array(std::ostringstream& os, const char* type, const char* nam
 
 static void emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
   const int ns = m.ns(), nr = m.nr();
-  for (const Reaction& r : m.reactions)
+  for (const Reaction& r : m.reactions) {
     if (r.sri) throw std::runtime_error("SRI falloff is supported for mechanisms of at most 24 state components");
+    if (r.kind == RxKind::Plog)
+      throw std::runtime_error("P-log reactions are supported for mechanisms of at most 24 state components");
+  }
   auto kind_of = [&](const Reaction& r) {
     if (r.kind == RxKind::Elementary) return 0;
     if (r.kind == RxKind::ThirdBody) return 1;

@@ -2,6 +2,7 @@
 // the same inputs: species thermo, stoichiometry, rate coefficients in SI units).
 #include "mechanism.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <stdexcept>
 
@@ -83,6 +84,8 @@ Mechanism parse_mechanism(const std::string& text) {
       rx.kind = RxKind::ThirdBody;
     else if (type == "falloff")
       rx.kind = RxKind::Falloff;
+    else if (type == "pressure-dependent-Arrhenius")
+      rx.kind = RxKind::Plog;
     else
       throw std::runtime_error("unsupported reaction type '" + type + "'");
     if (r.has("equation")) rx.equation = r["equation"].string();
@@ -111,10 +114,24 @@ Mechanism parse_mechanism(const std::string& text) {
         rx.sri_e = t.has("E") ? t["E"].number() : 0.0;
         if (!(rx.sri_c > 0.0) || !(rx.sri_d > 0.0)) throw std::runtime_error("SRI C and D must be positive");
       }
+    } else if (rx.kind == RxKind::Plog) {
+      for (auto& e : r["rate-constants"].arr) {
+        const double P = e["P"].number();
+        if (!(P > 0.0) || !std::isfinite(P)) throw std::runtime_error("P-log pressures must be positive");
+        rx.plog.emplace_back(std::log(P), read_arrhenius(e));
+      }
+      if (rx.plog.empty()) throw std::runtime_error("P-log reaction without rate constants");
+      std::sort(rx.plog.begin(), rx.plog.end(),
+                [](const std::pair<double, Arrhenius>& x, const std::pair<double, Arrhenius>& y) { return x.first < y.first; });
+      for (size_t i = 1; i < rx.plog.size(); ++i)
+        if (!(rx.plog[i].first > rx.plog[i - 1].first)) throw std::runtime_error("P-log pressures must be distinct");
+      rx.k = rx.plog.front().second;
     } else {
       rx.k = read_arrhenius(r["rate-constant"]);
     }
-    if (rx.kind != RxKind::Elementary) {
+    if (rx.kind == RxKind::Plog) {
+      rx.default_eff = 1.0;   // p = R T sum_i C_i: the rate depends on every concentration once
+    } else if (rx.kind != RxKind::Elementary) {
       if (r.has("default-efficiency")) rx.default_eff = r["default-efficiency"].number();
       if (r.has("efficiencies")) {
         for (auto& kv : r["efficiencies"].obj) {

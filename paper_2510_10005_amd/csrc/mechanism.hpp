@@ -9,7 +9,7 @@ namespace chem {
 
 constexpr double kR = 8314.462618;  // J/(kmol K)
 
-enum class RxKind { Elementary, ThirdBody, Falloff };
+enum class RxKind { Elementary, ThirdBody, Falloff, Plog };
 
 struct Arrhenius {
   double lnA = 0.0;   // ln of the prefactor (SI-kmol)
@@ -27,6 +27,7 @@ struct Reaction {
   bool troe = false;
   double troe_alpha = 0.0, troe_T3 = 0.0, troe_T1 = 0.0, troe_T2 = 0.0;
   bool troe_has_T2 = false;
+  std::vector<std::pair<double, Arrhenius>> plog;  // P-log: (ln p_i, rate) sorted by pressure; k = the first
   bool sri = false;   // SRI broadening F = d [a exp(-b/T) + exp(-T/c)]^X T^e
   double sri_a = 0.0, sri_b = 0.0, sri_c = 1.0, sri_d = 1.0, sri_e = 0.0;
   double default_eff = 1.0;

@@ -24,13 +24,28 @@ from _gpu import dev_soa, empty, gpu_mechanism, host_aos, integrated_state_error
 
 pytestmark = pytest.mark.gpu
 
-MECHS = ["tiny_5_6", "tiny_8_14", "h2like_10_27", "sri_12_30"]
+MECHS = ["tiny_5_6", "tiny_8_14", "h2like_10_27", "sri_12_30", "plog_12_30"]
+
+
+PLOG_OFF = ("the Rosenbrock adjoint is switched off for P-log mechanisms: on the GPU it returned NaN "
+            "(-O3) and O(1) errors (-O1) while a host build of the same kernel source matched the oracle "
+            "to 1e-15; the cause is not established")
 
 
 @pytest.fixture(scope="module", params=MECHS)
 def mechs(request):
+    if request.param == "plog_12_30":
+        pytest.skip(PLOG_OFF)
     print(f"[gpu] loading {request.param}", flush=True)
     return gpu_mechanism(request.param)
+
+
+def test_plog_tape_is_refused():
+    from paper_2510_10005_amd import CHEM_ROS2, Tape
+    from paper_2510_10005_amd._binding import ChemError
+    gm, _ = gpu_mechanism("plog_12_30")
+    with pytest.raises(ChemError, match="P-log"):
+        Tape(gm, 8, 2, method=CHEM_ROS2, max_steps=10)
 
 
 def _forward(gm, om, y0, opts, tape, ld):

@@ -51,7 +51,7 @@ def _build(generator, tmp_path, name):
     return exe, oracle.load_mechanism(path)
 
 
-@pytest.mark.parametrize("name", ["tiny_8_14", "h2like_10_27", "sri_12_30"])
+@pytest.mark.parametrize("name", ["tiny_8_14", "h2like_10_27", "sri_12_30", "plog_12_30"])
 @pytest.mark.parametrize("energy", [0, 1])
 def test_vjp_matches_oracle(generator, tmp_path, name, energy):
     exe, m = _build(generator, tmp_path, name)
