@@ -131,12 +131,16 @@ def _plog_rate(rx, j, T, lnT, invT, C, lnA):
     lnp = np.log(R * T * M)
     sets = rx.plog
     lnk = [lnA[j] + (lA - rx.lnA) + b * lnT - th * invT for _, lA, b, th in sets]
+    # term-wise size of each ln k_i: the rounding scale of a difference ln k_{i+1} - ln k_i
+    lnk_mag = [np.abs(lnA[j] + (lA - rx.lnA)) + abs(b) * np.abs(lnT) + abs(th) * np.abs(invT)
+               for _, lA, b, th in sets]
     dk = [(b + th * invT) * invT for _, _, b, th in sets]
     dk_mag = [(abs(b) + abs(th) * np.abs(invT)) * np.abs(invT) for _, _, b, th in sets]
     lr = np.real(lnp)
     out_k = lnk[0] + 0.0 * lnp
     out_dT = dk[0] + 0.0 * lnp
     out_dp = 0.0 * lnp
+    out_dp_mag = 0.0 * lr
     out_mag = dk_mag[0] + 0.0 * lr
     for i in range(len(sets) - 1):
         l0, l1 = sets[i][0], sets[i + 1][0]
@@ -145,15 +149,18 @@ def _plog_rate(rx, j, T, lnT, invT, C, lnA):
         out_k = np.where(inside, lnk[i] + w * (lnk[i + 1] - lnk[i]), out_k)
         out_dT = np.where(inside, (1.0 - w) * dk[i] + w * dk[i + 1], out_dT)
         out_dp = np.where(inside, (lnk[i + 1] - lnk[i]) / (l1 - l0), out_dp)
+        out_dp_mag = np.where(inside, (lnk_mag[i + 1] + lnk_mag[i]) / (l1 - l0), out_dp_mag)
         out_mag = np.where(inside, np.abs(1.0 - w) * dk_mag[i] + np.abs(w) * dk_mag[i + 1], out_mag)
     above = lr > sets[-1][0]
     out_k = np.where(above, lnk[-1], out_k)
     out_dT = np.where(above, dk[-1], out_dT)
     out_mag = np.where(above, dk_mag[-1], out_mag)
-    # d ln p / dT = 1/T and d ln p / dC_k = 1/sum C at fixed C and T
+    # d ln p / dT = 1/T and d ln p / dC_k = 1/sum C at fixed C and T.  The magnitudes of the
+    # p-derivative take the term-wise size of the two ln k it differences (they nearly cancel
+    # where two tabulated sets cross).
     dlnkf_dT = out_dT + out_dp * invT
-    mag_T = out_mag + np.abs(out_dp) * np.abs(invT)
-    return np.exp(out_k), dlnkf_dT, M, out_dp / M, mag_T, np.abs(out_dp) / np.abs(M)
+    mag_T = out_mag + out_dp_mag * np.abs(invT)
+    return np.exp(out_k), dlnkf_dT, M, out_dp / M, mag_T, out_dp_mag / np.abs(M)
 
 
 def _forward_rate(mech, rx, j, T, lnT, invT, C, lnA):

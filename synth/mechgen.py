@@ -91,6 +91,10 @@ MECH_CONFIGS = {
     # 12 species from {H, O, N}; 30 reactions: 8 P-log (3 pressures), 4 third-body, 2 Troe falloff
     "plog_12_30": MechConfig("plog_12_30", 1013, ("H", "O", "N"), 12, 30, 4, 2, 4, ("N2",), ("H2", "O2"),
                              n_plog=8),
+    # 30 species from {C, H, O, N} (the one-wavefront-per-cell form, n = 31); 90 reactions: 10 P-log,
+    # 6 falloff with SRI broadening, 8 third-body
+    "mix_30_90": MechConfig("mix_30_90", 1014, ("C", "H", "O", "N"), 30, 90, 8, 6, 5, ("N2",), ("H2", "O2"),
+                            broadening="sri", n_plog=10),
 }
 
 PLOG_PRESSURES = (1.0e4, 1.0e5, 1.0e6)   # Pa: the table straddles the workloads' ~1 atm

@@ -34,7 +34,7 @@ def _scaled_err(J, Jref):
     return np.where(scale > 0, diff / np.where(scale > 0, scale, 1.0), diff)
 
 
-@pytest.mark.parametrize("name", ["tiny_5_6", "tiny_8_14", "h2like_10_27", "sri_12_30", "plog_12_30", "ch4like_53_325"])
+@pytest.mark.parametrize("name", ["tiny_5_6", "tiny_8_14", "h2like_10_27", "sri_12_30", "plog_12_30", "mix_30_90", "ch4like_53_325"])
 @pytest.mark.parametrize("energy", [CONST_P, CONST_V])
 def test_jacobian_matches_complex_step(name, energy):
     from synth import mechanism_file

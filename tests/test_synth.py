@@ -9,7 +9,7 @@ from synth import generate_mechanism, MECH_CONFIGS
 from synth.states import sample_states
 
 
-@pytest.mark.parametrize("name", ["tiny_5_6", "tiny_8_14", "h2like_10_27", "sri_12_30", "plog_12_30", "ch4like_53_325"])
+@pytest.mark.parametrize("name", ["tiny_5_6", "tiny_8_14", "h2like_10_27", "sri_12_30", "plog_12_30", "mix_30_90", "ch4like_53_325"])
 def test_mechanism_structure(name):
     doc = generate_mechanism(name)
     cfg = MECH_CONFIGS[name]
