@@ -273,7 +273,7 @@ static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool ja
 }
 
 // Constant tables of the one-wave-per-cell form (large mechanisms): reactions at positions sorted
-// by rate form (elementary, third-body, Lindemann, Troe, Troe with T**) so that a round of 64
+// by rate form (elementary, third-body, Lindemann, Troe, Troe with T**, SRI, P-log) so that a round of 64
 // lanes mostly runs one branch; species reaction lists (CSR over positions) for the gathers.
 template <class T>
 static void emit_array(std::ostringstream& os, const char* type, const char* name, const std::vector<T>& v) {
@@ -291,14 +291,11 @@ static void emit_array(std::ostringstream& os, const char* type, const char* nam
 
 static void emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
   const int ns = m.ns(), nr = m.nr();
-  for (const Reaction& r : m.reactions) {
-    if (r.sri) throw std::runtime_error("SRI falloff is supported for mechanisms of at most 24 state components");
-    if (r.kind == RxKind::Plog)
-      throw std::runtime_error("P-log reactions are supported for mechanisms of at most 24 state components");
-  }
   auto kind_of = [&](const Reaction& r) {
     if (r.kind == RxKind::Elementary) return 0;
     if (r.kind == RxKind::ThirdBody) return 1;
+    if (r.kind == RxKind::Plog) return 6;
+    if (r.sri) return 5;
     if (!r.troe) return 2;
     return r.troe_has_T2 ? 4 : 3;
   };
@@ -325,8 +322,8 @@ static void emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
   }
   os << "#define WV_MR " << MR << "\n#define WV_MP " << MP << "\n#define WV_MN " << MN << "\n#define WV_ME " << ME
      << "\n#define WV_MD " << MD << "\n";
-  std::vector<int> rx, kind, rev, rs, rc, ps, pc, nus, es, ds;
-  std::vector<double> b, th, fo, tr, dnu, nuv, deff, ev;
+  std::vector<int> rx, kind, rev, rs, rc, ps, pc, nus, es, ds, plo, pln;
+  std::vector<double> b, th, fo, tr, dnu, nuv, deff, ev, sri, pl;
   for (int p = 0; p < nr; ++p) {
     const int j = pos[p];
     const Reaction& r = m.reactions[j];
@@ -343,6 +340,23 @@ static void emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
     tr.push_back(r.troe ? 1.0 / r.troe_T3 : 0.0);
     tr.push_back(r.troe ? 1.0 / r.troe_T1 : 0.0);
     tr.push_back(r.troe && r.troe_has_T2 ? r.troe_T2 : 0.0);
+    // SRI constants (a, b, 1/c, ln d, e) and P-log slices (ln p, ln A, b and Ea/R relative to the
+    // first set, then b and Ea/R) of the shared table
+    sri.push_back(r.sri ? r.sri_a : 0.0);
+    sri.push_back(r.sri ? r.sri_b : 0.0);
+    sri.push_back(r.sri ? 1.0 / r.sri_c : 0.0);
+    sri.push_back(r.sri ? std::log(r.sri_d) : 0.0);
+    sri.push_back(r.sri ? r.sri_e : 0.0);
+    plo.push_back(static_cast<int>(pl.size() / 6));
+    pln.push_back(static_cast<int>(r.plog.size()));
+    for (auto& e : r.plog) {
+      pl.push_back(e.first);
+      pl.push_back(e.second.lnA - r.plog.front().second.lnA);
+      pl.push_back(e.second.b - r.plog.front().second.b);
+      pl.push_back(e.second.theta - r.plog.front().second.theta);
+      pl.push_back(e.second.b);
+      pl.push_back(e.second.theta);
+    }
     deff.push_back(r.default_eff);
     for (int i = 0; i < MR; ++i) {
       const bool u = i < static_cast<int>(r.reactants.size());
@@ -387,6 +401,11 @@ static void emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
   emit_array(os, "double", "wv_th", th);
   emit_array(os, "double", "wv_fo", fo);
   emit_array(os, "double", "wv_tr", tr);
+  emit_array(os, "double", "wv_sri", sri);
+  emit_array(os, "int", "wv_plo", plo);
+  emit_array(os, "int", "wv_pln", pln);
+  if (pl.empty()) pl.assign(6, 0.0);
+  emit_array(os, "double", "wv_pl", pl);
   emit_array(os, "double", "wv_deff", deff);
   emit_array(os, "double", "wv_dnu", dnu);
   emit_array(os, "int", "wv_rs", rs);

@@ -19,7 +19,7 @@ from _gpu import dev_soa, empty, gpu_mechanism, host_aos, integrated_state_error
 
 pytestmark = pytest.mark.gpu
 
-MECHS = ["tiny_5_6", "tiny_8_14", "h2like_10_27", "sri_12_30", "plog_12_30", "ch4like_53_325"]
+MECHS = ["tiny_5_6", "tiny_8_14", "h2like_10_27", "sri_12_30", "plog_12_30", "mix_30_90", "ch4like_53_325"]
 
 
 @pytest.fixture(scope="module", params=MECHS)

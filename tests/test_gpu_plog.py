@@ -1,4 +1,5 @@
-"""GPU: P-log rates (Section 2.2) on the 12-species P-log mechanism at pressures from 3e3 to 3e6 Pa,
+"""GPU: P-log rates (Section 2.2) on the 12-species P-log mechanism (one cell per lane) and on the
+30-species mechanism with P-log and SRI reactions (one cell per wavefront) at pressures from 3e3 to 3e6 Pa,
 so that every interval of the pressure tables and both clamps are exercised (the other GPU tests
 run it at one atmosphere only).  Source terms and Jacobian within 1e-12 of the summed term
 magnitudes, both energy modes; backward-Euler and Rosenbrock integration with the oracle's step
@@ -23,6 +24,12 @@ def mechs():
     return gpu_mechanism("plog_12_30")
 
 
+@pytest.fixture(scope="module", params=["plog_12_30", "mix_30_90"])
+def any_form(request):
+    print(f"[gpu] loading {request.param}", flush=True)
+    return gpu_mechanism(request.param)
+
+
 def _states(om, n, seed):
     T, _, Y = sample_config("ros2_1m", om.ns, n)
     p = np.geomspace(3e3, 3e6, n)
@@ -31,8 +38,8 @@ def _states(om, n, seed):
 
 
 @pytest.mark.parametrize("energy", [0, 1])
-def test_plog_source_and_jacobian(mechs, energy):
-    gm, om = mechs
+def test_plog_source_and_jacobian(any_form, energy):
+    gm, om = any_form
     nc, ld = 240, 256
     y = _states(om, nc, 3 + energy)
     yd = dev_soa(y, ld)

@@ -1,6 +1,8 @@
 """CPU: the one-wavefront-per-cell integrators (mechanisms with 24 < n <= 64) against the oracle.
 
-The generated HIP source of the 53-species mechanism is compiled for the host together with a
+The generated HIP source of the 53-species mechanism, and of a 30-species one with SRI falloff and
+P-log reactions (run at 2e4 and 2e6 Pa, both intervals of its pressure tables), is compiled for the
+host together with a
 64-thread emulation of a wavefront (tests/emu/emu.hpp): every shuffle, ballot, readlane and
 barrier is a collective over all 64 lanes, so the run also checks that every lane reaches the
 same collectives (a lane that skips one deadlocks and the time limit reports it).  The GPU
@@ -27,8 +29,8 @@ CSRC = os.path.join(ROOT, "paper_2510_10005_amd", "csrc")
 EMU = os.path.join(ROOT, "tests", "emu")
 
 
-@pytest.fixture(scope="module")
-def emulator(tmp_path_factory):
+@pytest.fixture(scope="module", params=["ch4like_53_325", "mix_30_90"])
+def emulator(tmp_path_factory, request):
     cxx = shutil.which("g++")
     if cxx is None:
         pytest.skip("no host C++ compiler")
@@ -36,7 +38,7 @@ def emulator(tmp_path_factory):
     gen = str(d / "gen")
     subprocess.run([cxx, "-O1", "-std=c++17", "-I", CSRC, os.path.join(EMU, "gen_main.cpp"),
                     os.path.join(CSRC, "codegen.cpp"), os.path.join(CSRC, "mechanism.cpp"), "-o", gen], check=True)
-    path = mechanism_file("ch4like_53_325")
+    path = mechanism_file(request.param)
     with open(d / "src.hip", "w") as f:
         subprocess.run([gen, path], stdout=f, check=True)
     exe = str(d / "driver")
@@ -48,6 +50,8 @@ def emulator(tmp_path_factory):
 def _run(emulator, which, cfg, nc, dt, n_steps):
     exe, d, om = emulator
     T, p, Y = sample_config(cfg, om.ns, nc)
+    if any(rx.kind == "plog" for rx in om.reactions):
+        p = np.geomspace(2e4, 2e6, nc)          # both intervals of the P-log tables
     y0 = oracle.state_from_TPY(om, T, p, Y)
     ld = nc + 3
     ys = np.zeros((om.n, ld))
