@@ -158,10 +158,9 @@ const char* chem_last_error_message(void);
 
 /*
  * Load a mechanism file (Cantera-like JSON: species with NASA-7 data; reactions of type
- * elementary, three-body, falloff with Troe, SRI (Section 2.2; n <= 24 only) or Lindemann
- * broadening, or pressure-dependent-Arrhenius (P-log: {P [Pa], A, b, Ea} sets at distinct pressures,
- * ln k linear in ln p between them with p = R T sum C, the end sets outside; n <= 24 only); A, b, Ea
- * in SI-kmol with
+ * elementary, three-body, falloff with Troe, SRI (Section 2.2) or Lindemann broadening, or
+ * pressure-dependent-Arrhenius (P-log: {P [Pa], A, b, Ea} sets at distinct pressures, ln k linear
+ * in ln p between them with p = R T sum C, the end sets outside); A, b, Ea in SI-kmol with
  * Ea in J/kmol -- the units of the paper's worked example, Section 4.3), validate it, generate
  * HIP source specialised to it (the code-generation step of Section 4.3) and compile it for the
  * current device's architecture with hipRTC.  Compiled code objects are cached in cache_dir (or
