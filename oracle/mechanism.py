@@ -50,8 +50,15 @@ class Mechanism:
         self.E = np.array([[s["composition"].get(e, 0) for s in sp] for e in self.elements], dtype=float)
         self.p_ref = float(doc.get("reference-pressure", 101325.0))
         lo, hi, tmid = [], [], []
-        for s in sp:
+        self.poly = {}        # species index -> (cp/R coefficients a_0..a_np, h0, s0)
+        for i, s in enumerate(sp):
             th = s["thermo"]
+            if th["model"] == "polynomial-cp":
+                self.poly[i] = (np.array([float(v) for v in th["cp-R"]]), float(th["h0"]), float(th["s0"]))
+                tmid.append(1000.0)
+                lo.append([0.0] * 7)
+                hi.append([0.0] * 7)
+                continue
             assert th["model"] == "NASA7"
             tmid.append(float(th["temperature-ranges"][1]))
             lo.append([float(v) for v in th["data"][0]])

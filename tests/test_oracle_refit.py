@@ -1,0 +1,79 @@
+"""Pins of the oracle's single-range polynomial cp (Section 2.1, eq. specific_heat_polynomial and
+the enthalpy identity; Appendix C.1 varies its degree n_p) and of its refit from NASA-7 data:
+
+* a species whose NASA-7 cp is already one degree-4 polynomial over the whole range (both ranges
+  equal) is reproduced exactly by the refit with n_p = 4: cp, h and s at every temperature;
+* h and s of the refit equal the NASA-7 values at 298.15 K (the integration constants);
+* dh/dT = cp and ds/dT = cp/T for the refit species (complex-step derivatives), which pins the
+  integrated polynomials independently of their formulas;
+* the least-squares residual of cp on the fitting points decreases with n_p (4, 7, 10), as the
+  paper's degree study reports for the source error.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.mechanism import Mechanism
+from oracle.thermo import T_REF, nasa7_molar, refit_cp
+from synth import mechanism_file
+
+import json
+
+from test_oracle_integrators import _isomer_mech
+
+
+def test_exact_for_single_polynomial():
+    m = _isomer_mech()
+    m2 = Mechanism(refit_cp(m.doc, 4, 300.0, 3000.0))
+    T = np.linspace(300.0, 3000.0, 37)
+    a = nasa7_molar(m, T)
+    b = nasa7_molar(m2, T)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(y, x, rtol=1e-9, atol=1e-9)
+
+
+@pytest.fixture(scope="module")
+def h2_refit():
+    doc = json.load(open(mechanism_file("h2like_10_27")))
+    return Mechanism(doc), Mechanism(refit_cp(doc, 7))
+
+
+def test_reference_values_kept(h2_refit):
+    m, m7 = h2_refit
+    T = np.array([T_REF])
+    _, h, s, _, _ = nasa7_molar(m, T)
+    _, h7, s7, _, _ = nasa7_molar(m7, T)
+    np.testing.assert_allclose(h7, h, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(s7, s, rtol=1e-12, atol=1e-12)
+
+
+def test_derivative_identities(h2_refit):
+    _, m7 = h2_refit
+    T = np.linspace(400.0, 2900.0, 11)
+    hstep = 1e-30
+    cp, _, _, _, dcp = nasa7_molar(m7, T)
+    _, hc, sc, _, _ = nasa7_molar(m7, T + 1j * hstep)
+    # h/RT * R T = H: dH/dT / R = cp/R ; ds/dT = cp/T
+    dH = (np.imag(hc * (T + 1j * hstep)[:, None])) / hstep
+    np.testing.assert_allclose(dH, cp, rtol=1e-12)
+    np.testing.assert_allclose(np.imag(sc) / hstep, cp / T[:, None], rtol=1e-12)
+    cpc = nasa7_molar(m7, T + 1j * hstep)[0]
+    np.testing.assert_allclose(np.imag(cpc) / hstep, dcp, rtol=1e-10, atol=1e-14)
+
+
+def test_fit_error_decreases_with_degree():
+    """The least-squares residual on the fitting points cannot grow with n_p (nested polynomial
+    spaces); on this mechanism it falls strictly.  The points are the refit's 400 Chebyshev points
+    of [300, 3000] K."""
+    doc = json.load(open(mechanism_file("h2like_10_27")))
+    m = Mechanism(doc)
+    n = 400
+    T = 1650.0 + 1350.0 * np.cos(np.pi * (np.arange(n) + 0.5) / n)
+    cp = nasa7_molar(m, T)[0]
+    rms = []
+    for n_p in (4, 7, 10):
+        cpn = nasa7_molar(Mechanism(refit_cp(doc, n_p)), T)[0]
+        rms.append(np.sqrt(((cpn - cp) ** 2).mean(axis=0)))
+    assert np.all(rms[0] > rms[1]) and np.all(rms[1] > rms[2]), rms
+    assert (np.abs(nasa7_molar(Mechanism(refit_cp(doc, 7)), T)[0] - cp) / np.abs(cp)).max() < 5e-3
