@@ -291,6 +291,9 @@ static void emit_array(std::ostringstream& os, const char* type, const char* nam
 
 static void emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
   const int ns = m.ns(), nr = m.nr();
+  for (const Species& sp : m.species)
+    if (sp.poly)
+      throw std::runtime_error("polynomial-cp thermo is supported for mechanisms of at most 24 state components");
   auto kind_of = [&](const Reaction& r) {
     if (r.kind == RxKind::Elementary) return 0;
     if (r.kind == RxKind::ThirdBody) return 1;
@@ -487,6 +490,34 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
   // its range (T < T_mid: low, else high).  Variants return only what a caller needs.
   std::map<double, std::vector<int>> groups;
   for (int i = 0; i < ns; ++i) groups[m.species[i].T_mid].push_back(i);
+  // Single-range polynomial species (Section 2.1): cp/R = sum a_k T^k, h/RT = sum a_k T^k/(k+1)
+  // + h0/T, s/R = a_0 ln T + sum_(k>=1) a_k T^k/k + s0, d(cp/R)/dT = sum k a_k T^(k-1), in Horner form
+  auto horner = [&](const std::vector<double>& c) {
+    std::string e = num(c.back());
+    for (int k = static_cast<int>(c.size()) - 2; k >= 0; --k) e = num(c[k]) + " + T*(" + e + ")";
+    return e;
+  };
+  auto poly_cp = [&](const Species& s) { return horner(s.cp); };
+  auto poly_h = [&](const Species& s) {
+    std::vector<double> b(s.cp.size());
+    for (size_t k = 0; k < b.size(); ++k) b[k] = s.cp[k] / static_cast<double>(k + 1);
+    return horner(b) + " + " + num(s.h0) + "*invT";
+  };
+  auto poly_s = [&](const Species& s) {
+    std::string e = num(s.cp[0]) + "*lnT + " + num(s.s0);
+    if (s.cp.size() > 1) {
+      std::vector<double> c(s.cp.size() - 1);
+      for (size_t k = 1; k < s.cp.size(); ++k) c[k - 1] = s.cp[k] / static_cast<double>(k);
+      e += " + T*(" + horner(c) + ")";
+    }
+    return e;
+  };
+  auto poly_dcp = [&](const Species& s) {
+    if (s.cp.size() < 2) return std::string("0.0");
+    std::vector<double> d(s.cp.size() - 1);
+    for (size_t k = 1; k < s.cp.size(); ++k) d[k - 1] = static_cast<double>(k) * s.cp[k];
+    return horner(d);
+  };
   // what: bit 1 = cp, 2 = h, 4 = s, 8 = g (needs h and s), 16 = dcp
   auto emit_thermo = [&](const std::string& name, const std::string& params, int what) {
     os << "__device__ __forceinline__ void " << name << "(" << params << ") {\n";
@@ -496,7 +527,15 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
         const Species& s = m.species[i];
         const std::string I = std::to_string(i);
         os << "    { // " << s.name << "\n";
-        {  // select the coefficient set per lane, then Horner
+        if (s.poly) {
+          if (what & 1) os << "      cpR[" << I << "] = " << poly_cp(s) << ";\n";
+          if (what & 2 || what & 8) os << "      const double h_ = " << poly_h(s) << ";\n";
+          if (what & 2) os << "      hRT[" << I << "] = h_;\n";
+          if (what & 4 || what & 8) os << "      const double s_ = " << poly_s(s) << ";\n";
+          if (what & 4) os << "      sR[" << I << "] = s_;\n";
+          if (what & 8) os << "      gRT[" << I << "] = h_ - s_;\n";
+          if (what & 16) os << "      dcpR[" << I << "] = " << poly_dcp(s) << ";\n";
+        } else {  // select the coefficient set per lane, then Horner
           auto a = [&](int k) { return std::string("(hi ? ") + num(s.hi[k]) + " : " + num(s.lo[k]) + ")"; };
           if (what & 1) os << "      cpR[" << I << "] = " << a(0) << " + T*(" << a(1) << " + T*(" << a(2) << " + T*(" << a(3) << " + T*" << a(4) << ")));\n";
           if (what & 2 || what & 8)
@@ -673,6 +712,13 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
       const std::string I = std::to_string(i);
       auto a = [&](int k) { return std::string("(hi ? ") + num(sp.hi[k]) + " : " + num(sp.lo[k]) + ")"; };
       os << "    { // " << sp.name << "\n";
+      if (sp.poly) {
+        os << "      cpR[" << I << "] = " << poly_cp(sp) << ";\n";
+        os << "      hRT[" << I << "] = " << poly_h(sp) << ";\n";
+        os << "      gRT[" << I << "] = hRT[" << I << "] - (" << poly_s(sp) << ");\n";
+        os << "      dcpR[" << I << "] = " << poly_dcp(sp) << ";\n    }\n";
+        continue;
+      }
       os << "      cpR[" << I << "] = " << a(0) << " + T*(" << a(1) << " + T*(" << a(2) << " + T*(" << a(3) << " + T*"
          << a(4) << ")));\n";
       os << "      hRT[" << I << "] = " << a(0) << " + T*(0.5*" << a(1) << " + T*((1.0/3.0)*" << a(2) << " + T*(0.25*"

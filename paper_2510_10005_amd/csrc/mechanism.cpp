@@ -61,14 +61,25 @@ Mechanism parse_mechanism(const std::string& text) {
     if (!(sp.W > 0.0)) throw std::runtime_error("species '" + sp.name + "' has a non-positive molecular weight");
     if (s.has("inert") && s["inert"].kind == chemjson::Value::Bool) sp.inert = s["inert"].b;
     const auto& th = s["thermo"];
-    if (th["model"].string() != "NASA7") throw std::runtime_error("only NASA7 thermo is supported");
-    sp.T_mid = th["temperature-ranges"][1].number();
-    const auto& data = th["data"];
-    if (data.size() != 2 || data[0].size() != 7 || data[1].size() != 7)
-      throw std::runtime_error("NASA7 data must be two lists of 7 coefficients");
-    for (int k = 0; k < 7; ++k) {
-      sp.lo[k] = data[0][k].number();
-      sp.hi[k] = data[1][k].number();
+    const std::string model = th["model"].string();
+    if (model == "polynomial-cp") {
+      // single-range cp/R polynomial of degree n_p (Section 2.1) with its integration constants
+      sp.poly = true;
+      for (auto& v : th["cp-R"].arr) sp.cp.push_back(v.number());
+      if (sp.cp.empty() || sp.cp.size() > 32) throw std::runtime_error("cp-R must hold 1 to 32 coefficients");
+      sp.h0 = th["h0"].number();
+      sp.s0 = th["s0"].number();
+    } else if (model == "NASA7") {
+      sp.T_mid = th["temperature-ranges"][1].number();
+      const auto& data = th["data"];
+      if (data.size() != 2 || data[0].size() != 7 || data[1].size() != 7)
+        throw std::runtime_error("NASA7 data must be two lists of 7 coefficients");
+      for (int k = 0; k < 7; ++k) {
+        sp.lo[k] = data[0][k].number();
+        sp.hi[k] = data[1][k].number();
+      }
+    } else {
+      throw std::runtime_error("unsupported thermo model '" + model + "' (NASA7 or polynomial-cp)");
     }
     if (idx.count(sp.name)) throw std::runtime_error("duplicate species '" + sp.name + "'");
     idx[sp.name] = m.ns();

@@ -40,6 +40,9 @@ struct Species {
   double W = 0.0;                  // kg/kmol
   double T_mid = 1000.0;
   double lo[7] = {0}, hi[7] = {0};  // NASA-7 coefficients
+  bool poly = false;                // single-range cp/R = sum_k cp[k] T^k with integration constants
+  std::vector<double> cp;           // h0 (h/RT = (h0 + sum cp_k T^(k+1)/(k+1)) / T) and s0
+  double h0 = 0.0, s0 = 0.0;
   bool inert = false;
 };
 

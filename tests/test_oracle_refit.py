@@ -77,3 +77,14 @@ def test_fit_error_decreases_with_degree():
         rms.append(np.sqrt(((cpn - cp) ** 2).mean(axis=0)))
     assert np.all(rms[0] > rms[1]) and np.all(rms[1] > rms[2]), rms
     assert (np.abs(nasa7_molar(Mechanism(refit_cp(doc, 7)), T)[0] - cp) / np.abs(cp)).max() < 5e-3
+
+
+def test_library_refit_matches_oracle_refit():
+    """The package's refit utility (host preprocessing of a mechanism file) against the oracle's."""
+    from paper_2510_10005_amd.refit import refit_document
+    doc = json.load(open(mechanism_file("h2like_10_27")))
+    mo = Mechanism(refit_cp(doc, 7))
+    ml = Mechanism(refit_document(doc, 7))
+    T = np.linspace(300.0, 3000.0, 55)
+    for x, y in zip(nasa7_molar(mo, T), nasa7_molar(ml, T)):
+        np.testing.assert_allclose(y, x, rtol=1e-10, atol=1e-10)
