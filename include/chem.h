@@ -157,7 +157,10 @@ const char* chem_error_string(chem_err err);
 const char* chem_last_error_message(void);
 
 /*
- * Load a mechanism file (Cantera-like JSON: species with NASA-7 data; reactions of type
+ * Load a mechanism file (Cantera-like JSON: species with NASA-7 data, or with the single-range
+ * model {"model": "polynomial-cp", "cp-R": [a_0..a_np], "h0", "s0"} of Section 2.1 -- cp/R =
+ * sum a_k T^k, h/RT = sum a_k T^k/(k+1) + h0/T, s/R = a_0 ln T + sum_(k>=1) a_k T^k/k + s0; n <= 24
+ * only; reactions of type
  * elementary, three-body, falloff with Troe, SRI (Section 2.2) or Lindemann broadening, or
  * pressure-dependent-Arrhenius (P-log: {P [Pa], A, b, Ea} sets at distinct pressures, ln k linear
  * in ln p between them with p = R T sum C, the end sets outside); A, b, Ea in SI-kmol with
