@@ -264,8 +264,7 @@ chem_err chem_integrate(const chem_mech* mech, int64_t n_cells, int64_t ld, doub
 chem_err chem_tape_create(const chem_mech* mech, int64_t n_cells, int checkpoint_every, chem_tape** out);
 
 /* Tape for the discrete adjoint of the two-stage Rosenbrock method (Appendix A.3), n <= 24 only
- * (CHEM_EUNSUPPORTED otherwise), and not for mechanisms with P-log reactions (CHEM_EUNSUPPORTED:
- * switched off because its GPU results are wrong there for a reason not yet established).  chem_integrate with method CHEM_ROS2, the persistent form and
+ * (CHEM_EUNSUPPORTED otherwise).  chem_integrate with method CHEM_ROS2, the persistent form and
  * this tape records the initial states and the step size of every accepted step (8 B per step
  * and cell), on the device, allocated by that call; chem_integrate_adjoint rebuilds a checkpoint
  * every checkpoint_every accepted steps (8 n B per checkpoint and cell, in the tape) by replaying

@@ -660,12 +660,6 @@ chem_err chem_tape_create_ros2(const chem_mech* M, int64_t n_cells, int max_step
   if (n_cells < 0 || max_steps < 1 || ckpt_every < 1)
     return fail(CHEM_EINVAL, "n_cells >= 0, max_steps >= 1 and checkpoint_every >= 1 required");
   if (M->wave) return fail(CHEM_EUNSUPPORTED, kWaveIntegrationOff);
-  // The Rosenbrock adjoint of mechanisms with P-log reactions is switched off: on the GPU it
-  // returns wrong values (NaN at -O3, O(1) errors at -O1) while a host build of the same kernel
-  // source agrees with the reference; the cause is not established.
-  for (const auto& r : M->m.reactions)
-    if (r.kind == chem::RxKind::Plog)
-      return fail(CHEM_EUNSUPPORTED, "the Rosenbrock adjoint is not available for mechanisms with P-log reactions");
   chem_tape* t = new chem_tape();
   t->mech = M;
   t->method = CHEM_ROS2;

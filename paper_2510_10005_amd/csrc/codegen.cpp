@@ -738,7 +738,7 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
   // own terms: -s1/D + A s3 for k = 0, A cw_{k-1} otherwise), sig_j = sum_s nu_sj ut_s.  For
   // dual-number states y + eps d the dual parts are the directional derivatives along d.
   os << "template <class R, class GACC>\n"
-        "__device__ CHEM_EVAL_INLINE void mech_vjp(const R (&y)[NY], const double* __restrict__ lnA, int energy,"
+        "__device__ __noinline__ void mech_vjp(const R (&y)[NY], const double* __restrict__ lnA, int energy,"
         " const double (&u)[NY], R (&v)[NY], GACC& g, int gmode) {\n";
   os << "  const R T = y[0];\n  const R lnT = log(T);\n  const R invT = 1.0 / T;\n";
   os << "  R C[NS];\n#pragma unroll\n  for (int i = 0; i < NS; ++i) C[i] = y[1 + i];\n";

@@ -27,25 +27,10 @@ pytestmark = pytest.mark.gpu
 MECHS = ["tiny_5_6", "tiny_8_14", "h2like_10_27", "sri_12_30", "plog_12_30"]
 
 
-PLOG_OFF = ("the Rosenbrock adjoint is switched off for P-log mechanisms: on the GPU it returned NaN "
-            "(-O3) and O(1) errors (-O1) while a host build of the same kernel source matched the oracle "
-            "to 1e-15; the cause is not established")
-
-
 @pytest.fixture(scope="module", params=MECHS)
 def mechs(request):
-    if request.param == "plog_12_30":
-        pytest.skip(PLOG_OFF)
     print(f"[gpu] loading {request.param}", flush=True)
     return gpu_mechanism(request.param)
-
-
-def test_plog_tape_is_refused():
-    from paper_2510_10005_amd import CHEM_ROS2, Tape
-    from paper_2510_10005_amd._binding import ChemError
-    gm, _ = gpu_mechanism("plog_12_30")
-    with pytest.raises(ChemError, match="P-log"):
-        Tape(gm, 8, 2, method=CHEM_ROS2, max_steps=10)
 
 
 def _forward(gm, om, y0, opts, tape, ld):
@@ -95,7 +80,17 @@ def test_ros2_adjoint_matches_oracle(mechs, case):
     y0 = oracle.state_from_TPY(om, T, p, Y)
     ref = oracle.integrate_ros2(om, y0, dt, opt=oracle.IntegratorOptions(energy=energy), record=True,
                                 fixed_steps=fixed)
-    assert np.all(ref["status"] == 0)
+    if not np.all(ref["status"] == 0):
+        # a fixed step too long for a cell of this mechanism (the oracle's own run fails there):
+        # compare on the cells it integrates
+        keep = ref["status"] == 0
+        assert keep.mean() >= 0.9
+        y0 = y0[keep]
+        nc = int(keep.sum())
+        ld = nc + 3
+        ref = oracle.integrate_ros2(om, y0, dt, opt=oracle.IntegratorOptions(energy=energy), record=True,
+                                    fixed_steps=fixed)
+        assert np.all(ref["status"] == 0)
     w = loss_weights(nc, om.ns)
     _, lamN = final_loss(om, ref["y"], w)
     lam0_ref, g_ref = ros2_adjoint(om, lamN, y0, ref["history"], energy=energy)
