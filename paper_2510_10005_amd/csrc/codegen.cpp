@@ -478,6 +478,12 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
   os << "#if CHEM_DENSE\n#define CHEM_MUNROLL _Pragma(\"unroll\")\n#define CHEM_EVAL_INLINE __forceinline__\n"
         "#else\n#define CHEM_MUNROLL _Pragma(\"unroll 1\")\n#define CHEM_EVAL_INLINE __noinline__\n#endif\n";
   os << "#define CHEM_R 8314.462618\n";
+  // The Rosenbrock adjoint kernel calls the mechanism evaluation and the vector-Jacobian product out
+  // of line for mechanisms with P-log reactions (fully inlined there it computed wrong values on the
+  // GPU); inline otherwise.
+  bool any_plog = false;
+  for (auto& r : m.reactions) any_plog = any_plog || r.kind == RxKind::Plog;
+  os << "#define CHEM_ADJ_CALL " << (any_plog ? "__noinline__" : "CHEM_EVAL_INLINE") << "\n";
   os << "#define LNPREF_R " << num(std::log(m.p_ref / kR)) << "\n";
   os << "static __device__ const double mech_W[NS] = {";
   for (int i = 0; i < ns; ++i) os << (i ? ", " : "") << num(m.species[i].W);
@@ -738,7 +744,7 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
   // own terms: -s1/D + A s3 for k = 0, A cw_{k-1} otherwise), sig_j = sum_s nu_sj ut_s.  For
   // dual-number states y + eps d the dual parts are the directional derivatives along d.
   os << "template <class R, class GACC>\n"
-        "__device__ __noinline__ void mech_vjp(const R (&y)[NY], const double* __restrict__ lnA, int energy,"
+        "__device__ CHEM_ADJ_CALL void mech_vjp(const R (&y)[NY], const double* __restrict__ lnA, int energy,"
         " const double (&u)[NY], R (&v)[NY], GACC& g, int gmode) {\n";
   os << "  const R T = y[0];\n  const R lnT = log(T);\n  const R invT = 1.0 / T;\n";
   os << "  R C[NS];\n#pragma unroll\n  for (int i = 0; i < NS; ++i) C[i] = y[1 + i];\n";
