@@ -113,7 +113,9 @@ static void emit_rate(std::ostringstream& os, const Mechanism& m, int j, bool ja
       const Arrhenius& k = P[i].second;
       return std::string("((") + num(k.b) + " + " + num(k.theta) + "*invT)*invT)";
     };
-    os << "      if (chem_val(lnp) <= " << num(P[0].first) << ") { lk = " << set_lnk(0) << "; dkT = " << set_dT(0)
+    // !(lnp > p_0): a non-finite ln p (sum C <= 0 at a trial state) takes the lowest-pressure set,
+    // the rule of the table-driven form and of the reference evaluation
+    os << "      if (!(chem_val(lnp) > " << num(P[0].first) << ")) { lk = " << set_lnk(0) << "; dkT = " << set_dT(0)
        << "; dkp = 0.0; }\n";
     for (int i = 0; i + 1 < np; ++i) {
       const double inv = 1.0 / (P[i + 1].first - P[i].first);

@@ -95,6 +95,10 @@ MECH_CONFIGS = {
     # 6 falloff with SRI broadening, 8 third-body
     "mix_30_90": MechConfig("mix_30_90", 1014, ("C", "H", "O", "N"), 30, 90, 8, 6, 5, ("N2",), ("H2", "O2"),
                             broadening="sri", n_plog=10),
+    # 14 species from {C, H, O, N}, N2-like inert (13 active: the Rosenbrock kernels' packed upper
+    # factor needs 91 doubles per lane of LDS); 40 reactions: 4 third-body, 3 Troe falloff
+    "mid_14_40": MechConfig("mid_14_40", 1015, ("C", "H", "O", "N"), 14, 40, 4, 3, 5, ("N2",), ("H2", "O2"),
+                            isomers=True),
 }
 
 PLOG_PRESSURES = (1.0e4, 1.0e5, 1.0e6)   # Pa: the table straddles the workloads' ~1 atm

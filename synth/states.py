@@ -72,6 +72,12 @@ def paper_sampler(n_species: int, n_cells: int, seed: int):
     return T, p, Y
 
 
+def oracle_subset(n_total: int, n_subset: int = 16384, seed: int = 5000):
+    """Sorted indices of the seeded cell subset on which the CPU oracle is timed and checked."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.choice(n_total, size=min(n_subset, n_total), replace=False))
+
+
 def loss_weights(n_cells: int, n_species: int, seed: int = 3000):
     """w ~ N(0, 1) per (cell, species) for the scalar loss of the adjoint workload."""
     rng = np.random.Generator(np.random.PCG64(seed))
