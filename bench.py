@@ -49,7 +49,7 @@ def main():
     ap.add_argument("--skip-large", action="store_true", help="skip the 53-species mechanism legs")
     ap.add_argument("--probe", type=int, default=None,
                     help="probe_attempts of the persistent form (default: the library's)")
-    ap.add_argument("--cpu-cells", type=int, default=24)
+    ap.add_argument("--cpu-cells", type=int, default=128, help="oracle cells per host process")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the batched chemistry path here is single-device "
@@ -130,6 +130,8 @@ def main():
         f"{value:.3e} cell-substeps/s, {achieved / 1e12:.2f} TFLOP/s algorithmic, failed cells {n_fail}")
     sub = counters[0].to(torch.float64)
     imbalance = float(sub.max().item() / max(1.0, sub.median().item()))
+    # the persistent result of the timed steps, for the oracle's parity check on its subset
+    gpu_result = None if args.skip_cpu else (y.cpu().numpy(), counters.cpu().numpy())
 
     extras = {"persistent_launch": {"block": block, "grid": grid, "probe_attempts": opts.probe_attempts},
               "accepted_substeps_per_step": acc, "rejected_attempts_per_step": rej,
@@ -171,7 +173,8 @@ def main():
 
     cpu = None
     if not args.skip_cpu:
-        cpu = cpu_baseline(path, args.cpu_cells, cfg)
+        # the timed steps all integrate the same cells: y and counters hold the last step's result
+        cpu = cpu_baseline(path, args.cpu_cells, cfg, T, p, Y, *gpu_result)
 
     line = {
         "metric": "FP64 cell-substeps/sec + fraction of FP64 roofline; adjoint/forward time ratio",
@@ -511,25 +514,80 @@ def large_mechanism_legs(torch, np, dev, args):
     return out
 
 
-def cpu_baseline(path, n_cells, cfg):
-    """The CPU oracle, as it stands, on the first n_cells cells of the same workload (one thread)."""
+def _oracle_chunk(job):
+    """One worker of the CPU baseline: the oracle's Rosenbrock integration of a chunk of cells with
+    its BLAS limited to one thread."""
+    mech_path, y0, dt = job
     from threadpoolctl import threadpool_limits
 
     import oracle
-    from synth.states import sample_states
-    om = oracle.load_mechanism(path)
-    T, p, Y = sample_states(om.ns, n_cells, cfg.seed, cfg.T_range, cfg.alpha, cfg.p)
-    y0 = oracle.state_from_TPY(om, T, p, Y)
-    log(f"cpu oracle on {n_cells} cells")
+    om = oracle.load_mechanism(mech_path)
     with threadpool_limits(1):
         a = time.perf_counter()
-        r = oracle.integrate_ros2(om, y0, 1e-6)
+        r = oracle.integrate_ros2(om, y0, dt)
         wall = time.perf_counter() - a
-    acc = int(r["accepted"].sum())
-    log(f"cpu oracle: {acc} cell-substeps in {wall:.1f} s")
-    return {"value": acc / wall, "unit": "cell-substeps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_cells} cells of the same 1,048,576-cell workload, full 1e-6 s split step, "
-                      f"{acc} accepted substeps in {wall:.1f} s (NumPy FP64, BLAS limited to one thread)"}
+    return r["y"], r["status"], r["accepted"], r["rejected"], wall
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(path, cells_per_core, cfg, T, p, Y, y_gpu, counters_gpu):
+    """The CPU oracle, as it stands, on all host cores (at most 16, the box's share for one GPU):
+    one process per core, each integrating a chunk of cells_per_core cells of the seeded oracle
+    subset of the workload (seed 5000) over the full split step with one BLAS thread.  The rate is
+    the subset's accepted substeps over the wall time of the pool; the subset's final states are
+    compared with the GPU's (cells with equal step counts, integrated-state bar 1e-8)."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import oracle
+    from synth.states import oracle_subset
+    om = oracle.load_mechanism(path)
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    idx = oracle_subset(cfg.n_cells)[:cores * cells_per_core]
+    y0 = oracle.state_from_TPY(om, T[idx], p[idx], Y[idx])
+    chunks = [y0[k * cells_per_core:(k + 1) * cells_per_core] for k in range(cores)]
+    log(f"cpu oracle: {len(idx)} cells of the seed-5000 subset on {cores} processes")
+    ctx = mp.get_context("spawn")
+    a = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_chunk, [(path, c, 1e-6) for c in chunks])
+    wall = time.perf_counter() - a
+    yo = np.concatenate([r[0] for r in res])
+    so = np.concatenate([r[1] for r in res])
+    acc_o = np.concatenate([r[2] for r in res])
+    rej_o = np.concatenate([r[3] for r in res])
+    acc = int(acc_o.sum())
+    # parity on the subset
+    yg = y_gpu[:, idx].T
+    cg = counters_gpu[:, idx]
+    same = (cg[0] == acc_o) & (cg[1] == rej_o) & (so == 0)
+    rho = (yo[:, 1:] * om.W).sum(axis=1)
+    eT = np.abs(yg[:, 0] - yo[:, 0]) / np.abs(yo[:, 0])
+    Yg = yg[:, 1:] * om.W / rho[:, None]
+    Yo = yo[:, 1:] * om.W / rho[:, None]
+    eY = (np.abs(Yg - Yo) / np.maximum(np.abs(Yo), 1e-12)).max(axis=1)
+    err = np.maximum(eT, eY)
+    max_err = float(err[same].max()) if same.any() else None
+    log(f"cpu oracle: {acc} cell-substeps in {wall:.1f} s on {cores} processes; parity on {int(same.sum())} of "
+        f"{len(idx)} cells with equal step counts: max rel err {max_err}")
+    return {"value": acc / wall, "unit": "cell-substeps/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{len(idx)} cells of the seeded oracle subset (seed 5000) of the same 1,048,576-cell "
+                      f"workload, full 1e-6 s split step, {cells_per_core} cells per process on {cores} processes "
+                      f"(NumPy FP64, one BLAS thread each): {acc} accepted substeps in {wall:.1f} s",
+            "parity": {"cells": len(idx), "cells_same_step_counts": int(same.sum()),
+                       "max_rel_err_same_steps": max_err, "bar": 1e-8}}
 
 
 if __name__ == "__main__":

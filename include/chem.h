@@ -170,11 +170,13 @@ const char* chem_last_error_message(void);
  * $CHEM_KERNEL_CACHE, else a per-user temp directory) keyed by a hash of the generated source
  * and the compiler options.  The current HIP device at load time is the one the mechanism runs on.
  * State size n = species + 1 selects the kernel form: n <= 24 one cell per GPU lane with the
- * Jacobian and its LU in registers; 24 < n <= 64 one cell per 64-lane wavefront (row i of the
- * iteration matrix in lane i, reactions spread over the lanes, constants in generated tables);
- * n > 64 is rejected with CHEM_EUNSUPPORTED.  In this version chem_integrate, chem_autotune and
- * chem_integrate_adjoint return CHEM_EUNSUPPORTED for 24 < n <= 64 (the one-wavefront integrators
- * are built but switched off); the other entry points serve every supported size.
+ * Jacobian and its LU in registers (every method, form and adjoint); 24 < n <= 160 the block form,
+ * one cell per 256-thread workgroup with the species, reactions and matrix rows spread over the
+ * threads (constants in generated tables) and the iteration matrix factored by a pivoted LU whose
+ * updates run on the FP64 matrix cores (Section 3.4, direct solver).  In the block form
+ * chem_integrate and chem_autotune serve CHEM_BE and CHEM_ROS2 in the persistent form (the plain
+ * form, the other methods and adjoint tapes return CHEM_EUNSUPPORTED); its Jacobian API kernel runs
+ * one cell per 64-lane wavefront for n <= 64.  n > 160 is rejected with CHEM_EUNSUPPORTED.
  * On success *out owns the mechanism; release it with chem_free_mechanism.
  */
 chem_err chem_load_mechanism(const char* path, const char* cache_dir, chem_mech** out);

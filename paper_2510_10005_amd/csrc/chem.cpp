@@ -40,13 +40,9 @@ chem_err fail(chem_err e, const std::string& msg) {
 
 // Registers per lane beyond which the per-cell matrix lives in a device-memory workspace.
 constexpr int kDenseLimit = 24;  // n <= 24: one cell per lane, Jacobian and LU in registers
-constexpr int kWaveLimit = 64;   // 24 < n <= 64: one cell per wavefront (row per lane)
-// The one-wavefront-per-cell integrators (Rosenbrock, backward Euler, adjoint) are compiled and
-// verified on the CPU but not enabled: their first GPU run did not complete and the cause has not
-// been identified.
-const char* const kWaveIntegrationOff =
-    "integration of mechanisms with 24 < n <= 64 (one wavefront per cell) is switched off in this version: "
-    "its GPU run did not complete and the cause is not identified; chem_source_terms and chem_jacobian are available";
+constexpr int kWaveApiLimit = 64;  // 24 < n <= 64: API kernels with one cell per wavefront
+constexpr int kBlockLimit = 160;   // n > 24: integrators with one cell per 256-thread workgroup
+constexpr int kBlockThreads = 256;
 constexpr int kMaxBlock = 256;
 
 const char* kKernelNames[] = {
@@ -231,9 +227,9 @@ chem_err parse_file(const char* path, chem::Mechanism& m) {
   } catch (const std::exception& e) {
     return fail(CHEM_EPARSE, std::string(path) + ": " + e.what());
   }
-  if (m.n() > kWaveLimit)
+  if (m.n() > kBlockLimit)
     return fail(CHEM_EUNSUPPORTED, std::string(path) + ": " + std::to_string(m.ns()) +
-                                       " species; at most " + std::to_string(kWaveLimit - 1) + " are supported");
+                                       " species; at most " + std::to_string(kBlockLimit - 1) + " are supported");
   return CHEM_OK;
 }
 
@@ -280,13 +276,22 @@ struct chem_mech {
   std::vector<hipModule_t> modules;
   hipFunction_t fn[K_COUNT] = {};
   bool dense = true;
-  bool wave = false;  // one cell per 64-lane wavefront (blocks of 64)
+  bool wave = false;      // n > 24: table-driven evaluation; integrators one cell per 256-thread workgroup
+  bool wave_api = false;  // 24 < n <= 64: Jacobian API kernel one cell per 64-lane wavefront
+  int np = 0;             // padded matrix size of the block form (multiple of 16)
   DevBuf lnA_default, queue, ws, wst, counters_internal, running, seg, gws, gpart, sched, order, jstage;
   unsigned int* running_host = nullptr;
   int launch_block[5][2] = {};  // [method][form]
   int launch_grid[5][2] = {};
+  size_t max_shmem = 0;         // LDS bytes one block may use on this device
+  // The workspaces above are shared by every stream: each call that uses them records `fence` on
+  // its stream, and a call on another stream first waits for it (see StreamFence).
+  hipEvent_t fence = nullptr;
+  hipStream_t fence_stream = nullptr;
+  bool fence_set = false;
   std::mutex mu;
   ~chem_mech() {
+    if (fence) (void)hipEventDestroy(fence);
     if (running_host) (void)hipHostFree(running_host);
     for (hipModule_t md : modules) (void)hipModuleUnload(md);
   }
@@ -311,6 +316,31 @@ chem_err launch2d(const chem_mech* M, KernelId k, unsigned gx, unsigned gy, unsi
 }
 
 unsigned blocks_for(int64_t n, int block) { return static_cast<unsigned>((n + block - 1) / block); }
+
+// Orders a workspace-using call after the previous one on the same mechanism when the two were
+// enqueued on different streams; held under chem_mech::mu.  While the stream is being captured
+// into a graph nothing is waited on or recorded (the captured work is ordered by its replays).
+struct StreamFence {
+  chem_mech* M;
+  hipStream_t s;
+  bool capturing = false, armed = false;
+  StreamFence(chem_mech* m, hipStream_t st) : M(m), s(st) {}
+  chem_err begin() {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cs));
+    capturing = cs != hipStreamCaptureStatusNone;
+    if (!capturing && M->fence_set && M->fence_stream != s) HIP_TRY(hipStreamWaitEvent(s, M->fence, 0));
+    armed = true;
+    return CHEM_OK;
+  }
+  ~StreamFence() {
+    if (!armed || capturing) return;
+    if (hipEventRecord(M->fence, s) == hipSuccess) {
+      M->fence_stream = s;
+      M->fence_set = true;
+    }
+  }
+};
 
 chem_err check_cells(int64_t n_cells, int64_t ld) {
   if (n_cells < 0) return fail(CHEM_EINVAL, "n_cells must be >= 0");
@@ -391,6 +421,8 @@ unsigned shmem_for(const chem_mech* M, KernelId k, int block) {
   return static_cast<unsigned>(na * (na + 1) / 2) * static_cast<unsigned>(block) * sizeof(double);
 }
 
+bool shmem_fits(const chem_mech* M, KernelId k, int block) { return shmem_for(M, k, block) <= M->max_shmem; }
+
 // blocks per CU the runtime reports for a kernel at this block size (>= 1)
 int occupancy_blocks(const chem_mech* M, KernelId k, int block) {
   int nb = 0;
@@ -402,7 +434,9 @@ int occupancy_blocks(const chem_mech* M, KernelId k, int block) {
 
 void persistent_config(const chem_mech* M, int method, KernelId k, int& block, unsigned& grid) {
   block = M->launch_block[method][CHEM_PERSISTENT] ? M->launch_block[method][CHEM_PERSISTENT] : 64;
-  if (M->wave) block = 64;
+  if (M->wave) block = kBlockThreads;
+  // the Rosenbrock kernels' LDS grows with the block; 64 fits every register-resident size
+  while (block > 64 && !shmem_fits(M, k, block)) block /= 2;
   grid = M->launch_grid[method][CHEM_PERSISTENT]
              ? static_cast<unsigned>(M->launch_grid[method][CHEM_PERSISTENT])
              : static_cast<unsigned>(occupancy_blocks(M, k, block) * M->num_cu);
@@ -482,6 +516,7 @@ chem_err chem_load_mechanism(const char* path, const char* cache_dir, chem_mech*
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, M->device));
   M->num_cu = prop.multiProcessorCount;
+  M->max_shmem = prop.sharedMemPerBlock;
   std::string arch = prop.gcnArchName;
   M->arch = arch.substr(0, arch.find(':'));
   std::vector<CodeObject> objs;
@@ -494,10 +529,21 @@ chem_err chem_load_mechanism(const char* path, const char* cache_dir, chem_mech*
   }
   M->dense = M->m.n() <= kDenseLimit;
   M->wave = !M->dense;
+  M->wave_api = M->wave && M->m.n() <= kWaveApiLimit;
+  M->np = (M->m.n() + 15) / 16 * 16;
   for (int k = 0; k < K_COUNT; ++k) {
     if (M->wave && dense_only(k)) continue;
     hipModule_t md = M->modules[M->modules.size() == 1 ? 0 : kKernelGroup[k]];
-    HIP_TRY(hipModuleGetFunction(&M->fn[k], md, kKernelNames[k]));
+    const hipError_t ge = hipModuleGetFunction(&M->fn[k], md, kKernelNames[k]);
+    // the block form has no plain-form step kernels and no adjoint kernel: those stay null and the
+    // entry points that need them refuse the request
+    if (ge != hipSuccess && !(M->wave && (k == K_ROS2_STEP || k == K_BE_STEP || k == K_BE_ADJOINT))) {
+      HIP_TRY(ge);
+    }
+    if (ge != hipSuccess) {
+      M->fn[k] = nullptr;
+      (void)hipGetLastError();  // the expected miss must not stay the thread's last HIP error
+    }
   }
   {
     std::vector<bool> act(M->m.ns(), false);
@@ -512,6 +558,7 @@ chem_err chem_load_mechanism(const char* path, const char* cache_dir, chem_mech*
   if ((e = M->queue.ensure(sizeof(uint64_t)))) return e;
   if ((e = M->running.ensure(64 * sizeof(unsigned int)))) return e;
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&M->running_host), sizeof(unsigned int), hipHostMallocDefault));
+  HIP_TRY(hipEventCreateWithFlags(&M->fence, hipEventDisableTiming));
   *out = M.release();
   return CHEM_OK;
 }
@@ -574,6 +621,8 @@ chem_err chem_source_terms(const chem_mech* M, int64_t n, int64_t ld, const doub
   if (energy != CHEM_CONST_P && energy != CHEM_CONST_V) return fail(CHEM_EINVAL, "unknown energy mode");
   const double* la = lnA ? lnA : M->lnA_default.as<double>();
   void* args[] = {&n, &ld, &y, &la, &energy, &dydt};
+  if (M->wave && !M->wave_api)  // one cell per workgroup
+    return launch(M, K_SOURCE, static_cast<unsigned>(n), kBlockThreads, static_cast<hipStream_t>(stream), args);
   return launch(M, K_SOURCE, blocks_for(n, 256), 256, static_cast<hipStream_t>(stream), args);
 }
 
@@ -592,14 +641,17 @@ chem_err chem_jacobian(const chem_mech* M, int64_t n, int64_t ld, const double* 
     if (n == 0) return CHEM_OK;
     chem_mech* Mm = const_cast<chem_mech*>(M);
     std::lock_guard<std::mutex> lock(Mm->mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamFence fence(Mm, s);
+    if (chem_err e = fence.begin()) return e;
     if (chem_err e = Mm->jstage.ensure(sizeof(double) * static_cast<size_t>(chunk * NN))) return e;
     double* stage = Mm->jstage.as<double>();
-    hipStream_t s = static_cast<hipStream_t>(stream);
     for (int64_t c0 = 0; c0 < n; c0 += chunk) {
       int64_t nc = std::min(chunk, n - c0);
       {
         void* a[] = {&nc, &ld, &y, &la, &energy, &stage, &c0};
-        if (chem_err e = launch(M, K_JACOBIAN, static_cast<unsigned>(nc), 64, s, a)) return e;
+        if (chem_err e = launch(M, K_JACOBIAN, static_cast<unsigned>(nc), M->wave_api ? 64 : kBlockThreads, s, a))
+          return e;
       }
       {
         void* a[] = {&nc, &ld, &stage, &c0, &jac};
@@ -659,7 +711,7 @@ chem_err chem_tape_create_ros2(const chem_mech* M, int64_t n_cells, int max_step
   if (!M || !out) return fail(CHEM_EINVAL, "null argument");
   if (n_cells < 0 || max_steps < 1 || ckpt_every < 1)
     return fail(CHEM_EINVAL, "n_cells >= 0, max_steps >= 1 and checkpoint_every >= 1 required");
-  if (M->wave) return fail(CHEM_EUNSUPPORTED, kWaveIntegrationOff);
+  if (M->wave) return fail(CHEM_EUNSUPPORTED, "the Rosenbrock adjoint is implemented for n <= 24");
   chem_tape* t = new chem_tape();
   t->mech = M;
   t->method = CHEM_ROS2;
@@ -677,14 +729,55 @@ static chem_err fill_u64(chem_mech* M, uint64_t* p, int n, uint64_t v, hipStream
   return launch(M, K_FILL_U64, blocks_for(n, 64), 64, s, args);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device workspaces supplied by the caller of integrate_impl instead of the mechanism's own
+// buffers (the allocation-free entry point).  Sized for n <= max_cells and, when counters is
+// used, ld <= max_cells.
+struct FixedWorkspace {
+  uint64_t* queue;
+  unsigned int* sched;
+  double* wst;
+  int* order;
+  int* counters;
+  int64_t max_cells;
+};
+
+chem_err integrate_impl(chem_mech* M, int64_t n, int64_t ld, double* y, const double* lnA,
+                        const chem_integrator_opts* opts, chem_tape* tape, int32_t* status, int32_t* counters,
+                        void* stream, const FixedWorkspace* fw);
+
+}  // namespace
+
+extern "C" {
+
 chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, const double* lnA,
                         const chem_integrator_opts* opts, chem_tape* tape, int32_t* status, int32_t* counters,
                         void* stream) {
-  chem_mech* M = const_cast<chem_mech*>(Mc);
+  return integrate_impl(const_cast<chem_mech*>(Mc), n, ld, y, lnA, opts, tape, status, counters, stream, nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+
+chem_err integrate_impl(chem_mech* M, int64_t n, int64_t ld, double* y, const double* lnA,
+                        const chem_integrator_opts* opts, chem_tape* tape, int32_t* status, int32_t* counters,
+                        void* stream, const FixedWorkspace* fw) {
   if (!M || !y || !status) return fail(CHEM_EINVAL, "null argument");
   if (chem_err e = check_cells(M, n, ld)) return e;
   if (chem_err e = validate_opts(opts)) return e;
-  if (M->wave) return fail(CHEM_EUNSUPPORTED, kWaveIntegrationOff);
+  if (M->wave) {
+    // the block form (n > 24): backward Euler and Rosenbrock, persistent form, no tape yet
+    if (opts->method != CHEM_BE && opts->method != CHEM_ROS2)
+      return fail(CHEM_EUNSUPPORTED, std::string(method_name(opts->method)) + " is implemented for n <= 24");
+    if (opts->form != CHEM_PERSISTENT)
+      return fail(CHEM_EUNSUPPORTED, "mechanisms with n > 24 integrate in the persistent form");
+    if (tape && !M->fn[K_BE_ADJOINT])
+      return fail(CHEM_EUNSUPPORTED, "no adjoint tape for mechanisms with n > 24 in this version");
+  }
   if (persistent_only(opts->method)) {
     if (opts->form != CHEM_PERSISTENT)
       return fail(CHEM_EUNSUPPORTED, std::string(method_name(opts->method)) + " runs in the persistent form only");
@@ -693,6 +786,9 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
   if (tape) {
     if (tape->mech != M) return fail(CHEM_EINVAL, "tape belongs to another mechanism");
     if (tape->method != opts->method) return fail(CHEM_EINVAL, "tape was created for another method");
+    // the backward-Euler tape stores each step's substep count (at most 2^depth) as 16 bits
+    if (tape->method == CHEM_BE && opts->halving_max_depth > 15)
+      return fail(CHEM_EINVAL, "halving_max_depth <= 15 is required when recording a backward-Euler tape");
     if (tape->n_cells < n) return fail(CHEM_EINVAL, "tape was created for fewer cells");
     if (tape->method == CHEM_ROS2 && opts->form != CHEM_PERSISTENT)
       return fail(CHEM_EUNSUPPORTED, "Rosenbrock recording runs in the persistent form");
@@ -700,12 +796,16 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
   if (n == 0) return CHEM_OK;
   std::lock_guard<std::mutex> lock(M->mu);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  StreamFence fence(M, s);
+  if (chem_err e = fence.begin()) return e;
   const double* la = lnA ? lnA : M->lnA_default.as<double>();
   const int NY = M->m.n();
   DevChemOpts o = to_dev(*opts, tape ? tape->ckpt_every : 1);
   chem_err e;
   int* cnt = counters;
-  if (!cnt) {
+  if (!cnt && fw) {
+    cnt = fw->counters;
+  } else if (!cnt) {
     if ((e = M->counters_internal.ensure(sizeof(int) * 3 * static_cast<size_t>(ld)))) return e;
     cnt = M->counters_internal.as<int>();
   }
@@ -751,11 +851,12 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
     persistent_config(M, method, k, block, grid);
     int64_t slots = static_cast<int64_t>(grid) * block;
     double* ws = nullptr;
-    if (!M->dense && !M->wave) {
-      if ((e = M->ws.ensure(sizeof(double) * static_cast<size_t>(NY) * NY * slots))) return e;
+    if (M->wave && M->np > 64) {
+      // the block form's matrix stores: one padded np x np matrix per workgroup of the grid
+      if ((e = M->ws.ensure(sizeof(double) * static_cast<size_t>(M->np) * M->np * grid))) return e;
       ws = M->ws.as<double>();
     }
-    uint64_t* q = M->queue.as<uint64_t>();
+    uint64_t* q = fw ? fw->queue : M->queue.as<uint64_t>();
     if ((e = fill_u64(M, q, 1, 0, s))) return e;
     if (method == CHEM_YASS) {
       DevYassOpts yo = yass_to_dev(*opts);
@@ -773,13 +874,19 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
       unsigned int* sched = nullptr;
       if (budget > 0) {
         // probe launch, bins of the parked cells, resume launch in that order (no host sync)
-        if ((e = M->wst.ensure(sizeof(double) * 4 * static_cast<size_t>(n)))) return e;
-        if ((e = M->order.ensure(sizeof(int) * static_cast<size_t>(n)))) return e;
-        // [0] parked count, [1, 1 + bins) bin counts, [1 + bins, 1 + 2 bins) bin offsets, 1 pad word
-        if ((e = M->sched.ensure(sizeof(unsigned int) * (2 + 2 * kSchedBins)))) return e;
-        wst = M->wst.as<double>();
-        order = M->order.as<int>();
-        sched = M->sched.as<unsigned int>();
+        if (fw) {
+          wst = fw->wst;
+          order = fw->order;
+          sched = fw->sched;
+        } else {
+          if ((e = M->wst.ensure(sizeof(double) * 4 * static_cast<size_t>(n)))) return e;
+          if ((e = M->order.ensure(sizeof(int) * static_cast<size_t>(n)))) return e;
+          // [0] parked count, [1, 1 + bins) bin counts, [1 + bins, 1 + 2 bins) bin offsets, 1 pad word
+          if ((e = M->sched.ensure(sizeof(unsigned int) * (2 + 2 * kSchedBins)))) return e;
+          wst = M->wst.as<double>();
+          order = M->order.as<int>();
+          sched = M->sched.as<unsigned int>();
+        }
         if ((e = fill_u64(M, reinterpret_cast<uint64_t*>(sched), (2 + 2 * kSchedBins) / 2, 0, s))) return e;
       }
       const int* no_order = nullptr;
@@ -861,6 +968,10 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
   return CHEM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 // Reverse sweep of a Rosenbrock tape: one lane per cell (static grid-stride mapping), segment
 // states in M->seg, per-block ln A partial sums reduced in block order.
 static chem_err ros2_adjoint(chem_mech* M, chem_tape* tape, const double* la, const double* dLdyN, double* dLdy0,
@@ -898,10 +1009,12 @@ chem_err chem_integrate_adjoint(const chem_mech* Mc, chem_tape* tape, const doub
   chem_mech* M = const_cast<chem_mech*>(Mc);
   if (!M || !tape || !dLdyN || !dLdy0 || !dLdlnA) return fail(CHEM_EINVAL, "null argument");
   if (tape->mech != M) return fail(CHEM_EINVAL, "tape belongs to another mechanism");
-  if (M->wave) return fail(CHEM_EUNSUPPORTED, kWaveIntegrationOff);
+  if (M->wave && !M->fn[K_BE_ADJOINT]) return fail(CHEM_EUNSUPPORTED, "no adjoint for mechanisms with n > 24 in this version");
   if (!tape->recorded) return fail(CHEM_EINVAL, "tape holds no recorded forward run");
   std::lock_guard<std::mutex> lock(M->mu);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  StreamFence fence(M, s);
+  if (chem_err e = fence.begin()) return e;
   int64_t n = tape->n_cells, ld = tape->ld;
   const double* la = lnA ? lnA : M->lnA_default.as<double>();
   const int NY = M->m.n(), NR = std::max(1, M->m.nr());
@@ -946,7 +1059,14 @@ chem_err chem_set_launch(chem_mech* M, int method, int form, int block, int grid
     return fail(CHEM_EINVAL, "unknown method or form");
   if (block != 0 && (block < 64 || block > kMaxBlock || block % 64)) return fail(CHEM_EINVAL, "block must be 64..256, a multiple of 64");
   if (grid < 0) return fail(CHEM_EINVAL, "grid must be >= 0");
-  M->launch_block[method][form] = M->wave && block != 0 ? 64 : block;
+  if (block != 0 && method == CHEM_ROS2 && !M->wave) {
+    const KernelId k = form == CHEM_PERSISTENT ? K_ROS2_PERSISTENT : K_ROS2_STEP;
+    if (!shmem_fits(M, k, block))
+      return fail(CHEM_EINVAL, "block " + std::to_string(block) + " needs " + std::to_string(shmem_for(M, k, block)) +
+                                   " B of LDS for the Rosenbrock kernel; the device allows " +
+                                   std::to_string(M->max_shmem));
+  }
+  M->launch_block[method][form] = M->wave && block != 0 ? kBlockThreads : block;
   M->launch_grid[method][form] = grid;
   return CHEM_OK;
 }
@@ -963,7 +1083,7 @@ chem_err chem_get_launch(const chem_mech* M, int method, int form, int* block, i
     *block = b;
     *grid = static_cast<int>(g);
   } else {
-    *block = M->wave ? 64 : (M->launch_block[method][form] ? M->launch_block[method][form] : 64);
+    *block = M->wave ? kBlockThreads : (M->launch_block[method][form] ? M->launch_block[method][form] : 64);
     *grid = 0;
   }
   return CHEM_OK;
@@ -975,7 +1095,8 @@ chem_err chem_autotune(chem_mech* M, int64_t n, int64_t ld, const double* y, con
   if (chem_err e = check_cells(M, n, ld)) return e;
   if (chem_err e = validate_opts(opts)) return e;
   if (opts->form != CHEM_PERSISTENT) return fail(CHEM_EUNSUPPORTED, "autotuning covers the persistent form");
-  if (M->wave) return fail(CHEM_EUNSUPPORTED, kWaveIntegrationOff);
+  if (M->wave && opts->method != CHEM_BE && opts->method != CHEM_ROS2)
+    return fail(CHEM_EUNSUPPORTED, std::string(method_name(opts->method)) + " is implemented for n <= 24");
   if (n == 0) return CHEM_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int NY = M->m.n();
@@ -990,20 +1111,28 @@ chem_err chem_autotune(chem_mech* M, int64_t n, int64_t ld, const double* y, con
   float best = 1e30f;
   int best_block = 64, best_grid = 0;
   const int method = opts->method;
+  const int prev_block = M->launch_block[method][CHEM_PERSISTENT], prev_grid = M->launch_grid[method][CHEM_PERSISTENT];
+  // one timed trial of a launch shape on a copy of the cells
+  auto trial = [&](int block, int grid, float& ms) -> chem_err {
+    if (chem_err err = chem_set_launch(M, method, CHEM_PERSISTENT, block, grid)) return err;
+    HIP_TRY(hipMemcpyAsync(ycopy.p, y, sizeof(double) * NY * static_cast<size_t>(ld), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipEventRecord(a, s));
+    chem_err err = chem_integrate(M, n, ld, ycopy.as<double>(), lnA, opts, nullptr, st.as<int>(), nullptr, stream);
+    HIP_TRY(hipEventRecord(b, s));
+    HIP_TRY(hipEventSynchronize(b));
+    if (err) return err;
+    HIP_TRY(hipEventElapsedTime(&ms, a, b));
+    return CHEM_OK;
+  };
+  e = CHEM_OK;
   for (int block : {64, 128, 256}) {
-    if (M->wave && block != 64) continue;  // one cell per 64-lane block
+    if (M->wave && block != kBlockThreads) continue;  // one cell per 256-thread workgroup
+    if (!shmem_fits(M, k, block)) continue;  // the Rosenbrock kernels' LDS grows with the block
     const int occ = occupancy_blocks(M, k, block);
     for (int mult : {1, 2}) {
       const int grid = occ * M->num_cu * mult;
-      if ((e = chem_set_launch(M, method, CHEM_PERSISTENT, block, grid))) break;
-      HIP_TRY(hipMemcpyAsync(ycopy.p, y, sizeof(double) * NY * static_cast<size_t>(ld), hipMemcpyDeviceToDevice, s));
-      HIP_TRY(hipEventRecord(a, s));
-      e = chem_integrate(M, n, ld, ycopy.as<double>(), lnA, opts, nullptr, st.as<int>(), nullptr, stream);
-      HIP_TRY(hipEventRecord(b, s));
-      HIP_TRY(hipEventSynchronize(b));
-      if (e) break;
       float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, a, b));
+      if ((e = trial(block, grid, ms))) break;
       if (ms < best) {
         best = ms;
         best_block = block;
@@ -1014,7 +1143,12 @@ chem_err chem_autotune(chem_mech* M, int64_t n, int64_t ld, const double* y, con
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  if (e) return e;
+  if (e) {
+    // a failed trial leaves the configuration the mechanism had before
+    M->launch_block[method][CHEM_PERSISTENT] = prev_block;
+    M->launch_grid[method][CHEM_PERSISTENT] = prev_grid;
+    return e;
+  }
   return chem_set_launch(M, method, CHEM_PERSISTENT, best_block, best_grid);
 }
 

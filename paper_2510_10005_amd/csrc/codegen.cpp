@@ -29,6 +29,23 @@ static const char* kKernels =
 static const char* kWave =
 #include "device_wave.inc"
     ;
+static const char* kBlock =
+#include "device_block.inc"
+    ;
+
+// Rows of the Jacobian assembled per LDS part in the block form: the whole padded matrix when it
+// is at most 64 (the factors then stay in LDS), else what fits the workgroup's LDS (160 KiB on
+// gfx950) beside the records and vectors; mirrors the size of BkShared in device_block.inc.
+static int block_part_rows(int n, int nr, int md) {
+  const int np = (n + 15) / 16 * 16, js = np + 1;
+  if (np <= 64) return np;
+  const long fixed = 8L * (13L * np + 16 + static_cast<long>(nr) * (3 + md) + 10L * np + 8) + 4L * (2L * np + 8) + 64;
+  const long budget = 163840 - 1024 - fixed;
+  long rows = budget / (8L * js);
+  if (rows > np) rows = np;
+  if (rows < 16) throw std::runtime_error("mechanism too large for the block form's LDS");
+  return static_cast<int>(rows);
+}
 
 static std::string num(double v) {
   char buf[64];
@@ -291,7 +308,8 @@ static void emit_array(std::ostringstream& os, const char* type, const char* nam
   os << "};\n";
 }
 
-static void emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
+// returns the number of derivative-record species per reaction (WV_MD)
+static int emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
   const int ns = m.ns(), nr = m.nr();
   for (const Species& sp : m.species)
     if (sp.poly)
@@ -468,6 +486,7 @@ static void emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
   }
   emit_array(os, "double", "wv_nasa", nasa);
   emit_array(os, "double", "wv_tmid", tmid);
+  return MD;
 }
 
 std::string generate_source(const Mechanism& m, int dense_limit) {
@@ -592,7 +611,10 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
 
   const bool wave = n > dense_limit;
   os << "#define CHEM_WAVE " << (wave ? 1 : 0) << "\n";
-  if (wave) {
+  // n <= 64: the API kernels of the one-wavefront-per-cell form; larger: those of the block form
+  const bool wave_api = n <= 64;
+  os << "#define CHEM_WAVE_API " << (wave && wave_api ? 1 : 0) << "\n";
+  if (wave && wave_api) {
     // source terms alone need only C, g/RT and the production rates per cell, few enough values
     // for one cell per lane with the constants folded into straight-line code (API kernel)
     os << "__device__ void mech_source_lane(const double (&y)[NY], const double* __restrict__ lnA, int energy,"
@@ -619,9 +641,13 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
     os << "#pragma unroll\n  for (int i = 0; i < NS; ++i) {\n    N = fma(hRT[i] - off, w[i], N);\n"
           "    D = fma(C[i], cpR[i] - off, D);\n  }\n";
     os << "  S[0] = -T * N / D;\n#pragma unroll\n  for (int i = 0; i < NS; ++i) S[1 + i] = w[i];\n}\n";
-    emit_wave_tables(os, m);
+  }
+  if (wave) {
+    const int md = emit_wave_tables(os, m);
+    os << "#define BK_PART " << block_part_rows(n, nr > 0 ? nr : 1, md) << "\n";
     os << kKernels;
     os << kWave;
+    os << kBlock;
     return os.str();
   }
 

@@ -1,10 +1,12 @@
-// CPU emulation of one 64-lane HIP workgroup with cooperative fibers: the 64 lanes are ucontext
-// fibers on one host thread that switch round-robin at every wave collective (shuffle, ballot,
-// readlane, barrier).  Each collective is double-buffered by its sequence number, and every lane
-// records the source line of the collective it reached: when the lanes of the wave are not all at
-// the same collective (a divergent exit from a loop that contains collectives, or a lane that
-// ends the kernel while others continue), the emulator prints both lines and exits with status 9
-// instead of blocking.  __shared__ arrays become statics (blocks run one after another).
+// CPU emulation of one HIP workgroup of 64 or 256 threads (one or four 64-lane wavefronts) with
+// cooperative fibers: the threads are ucontext fibers on one host thread that switch round-robin
+// at every wave collective (shuffle, ballot, readlane, FP64 matrix-core product) and at every
+// workgroup barrier.  Wave collectives are double-buffered by their sequence number, and every lane
+// records the source line of the collective it reached: when the lanes of a wave are not all at
+// the same collective (a divergent exit from a loop that contains collectives, or a lane that ends
+// the kernel while others continue), or the threads of the workgroup are not all at the same
+// barrier, the emulator prints the lines and exits with status 9 instead of blocking.  __shared__
+// variables become statics (workgroups run one after another).
 #pragma once
 #include <ucontext.h>
 
@@ -21,154 +23,215 @@ using std::fmin; using std::log2;
 #define __host__
 #define __forceinline__ inline
 #define __noinline__
-#define __launch_bounds__(x)
+#define __launch_bounds__(...)
 #define __shared__ static
 #define __restrict__
 struct Dim3 { unsigned x = 0, y = 0, z = 0; };
 
 namespace emu {
-constexpr int kLanes = 64;
-struct Wave {
-  ucontext_t main_ctx, ctx[kLanes];
-  int lane = 0;                 // running lane
-  bool done[kLanes] = {};
-  long long seq[kLanes] = {};   // collectives reached per lane (at its end, for a finished lane)
-  uint64_t slot[2][kLanes];
-  int site[2][kLanes];
+constexpr int kMaxThreads = 256;
+struct Block {
+  ucontext_t main_ctx, ctx[kMaxThreads];
+  int nthreads = 64;
+  int cur = 0;                        // running thread
+  bool done[kMaxThreads] = {};
+  long long seq[kMaxThreads] = {};    // wave collectives reached per thread
+  long long bars[kMaxThreads] = {};   // barriers reached per thread
+  int bar_site[kMaxThreads] = {};
+  uint64_t slot[2][kMaxThreads];
+  double ma[2][kMaxThreads], mb[2][kMaxThreads];
+  int site[2][kMaxThreads];
   long long collectives = 0;
 };
-inline Wave* g_wave = nullptr;
+inline Block* g_blk = nullptr;
 inline Dim3 g_block, g_dim, g_grid;
+// called before every workgroup starts (a driver poisons the emulated LDS with it: on the GPU a
+// workgroup's LDS holds stale values, here statics would otherwise start zeroed)
+inline void (*g_block_start)() = nullptr;
 
 [[noreturn]] inline void diverged(const char* what, int a, int sa, int b, int sb) {
-  std::fprintf(stderr, "wave divergence (%s): lane %d at line %d, lane %d at line %d\n", what, a, sa, b, sb);
+  std::fprintf(stderr, "divergence (%s): thread %d at line %d, thread %d at line %d\n", what, a, sa, b, sb);
   std::fflush(stderr);
   std::_Exit(9);
 }
 
-// switch to the next lane that has not finished (round-robin); a lane that finished while others
-// still reach collectives is reported by the caller's check
+// switch to the next thread that has not finished (round-robin)
 inline void yield_next() {
-  Wave& w = *g_wave;
-  const int me = w.lane;
-  for (int s = 1; s <= kLanes; ++s) {
-    const int nx = (me + s) % kLanes;
-    if (w.done[nx]) continue;
+  Block& B = *g_blk;
+  const int me = B.cur;
+  for (int s = 1; s <= B.nthreads; ++s) {
+    const int nx = (me + s) % B.nthreads;
+    if (B.done[nx]) continue;
     if (nx == me) return;
-    w.lane = nx;
-    swapcontext(&w.ctx[me], &w.ctx[nx]);
+    B.cur = nx;
+    swapcontext(&B.ctx[me], &B.ctx[nx]);
     return;
+  }
+}
+
+// write this lane's part of wave collective k, yield, check that the whole wave wrote it
+inline int wave_arrive(int line, long long& k) {
+  Block& B = *g_blk;
+  const int me = B.cur;
+  k = B.seq[me]++;
+  const int b = static_cast<int>(k & 1);
+  B.site[b][me] = line;
+  if (me == 0) ++B.collectives;
+  return b;
+}
+inline void wave_check(long long k, int b, int line) {
+  Block& B = *g_blk;
+  const int me = B.cur, w0 = me & ~63;
+  for (int l = w0; l < w0 + 64; ++l) {
+    // lanes earlier in the round may already have gone on (or finished) after this collective
+    if (B.seq[l] < k + 1) diverged("lane of the wave finished before this collective", l, B.site[b][l], me, line);
+    if (B.site[b][l] != line) diverged("lanes of one wave at different collectives", l, B.site[b][l], me, line);
   }
 }
 
 template <class T>
 inline T exchange(T v, int src, int line) {
   static_assert(sizeof(T) <= 8, "");
-  Wave& w = *g_wave;
-  const int me = w.lane;
-  const long long k = w.seq[me]++;
-  const int b = static_cast<int>(k & 1);
+  Block& B = *g_blk;
+  long long k;
+  const int b = wave_arrive(line, k);
   uint64_t bits = 0;
   std::memcpy(&bits, &v, sizeof(T));
-  w.slot[b][me] = bits;
-  w.site[b][me] = line;
-  if (me == 0) ++w.collectives;
+  B.slot[b][B.cur] = bits;
   yield_next();
-  // every lane has now written collective k
-  for (int l = 0; l < kLanes; ++l) {
-    // lanes earlier in this round may already have gone on (or finished) after this collective
-    if (w.seq[l] < k + 1) diverged("lane finished before this collective", l, w.site[b][l], me, line);
-    if (w.site[b][l] != line) diverged("different collectives", l, w.site[b][l], me, line);
-  }
+  wave_check(k, b, line);
   T r;
-  std::memcpy(&r, &w.slot[b][src & 63], sizeof(T));
+  std::memcpy(&r, &B.slot[b][(B.cur & ~63) + (src & 63)], sizeof(T));
   return r;
 }
 inline unsigned long long ballot(bool p, int line) {
-  Wave& w = *g_wave;
-  const int me = w.lane;
-  const long long k = w.seq[me]++;
-  const int b = static_cast<int>(k & 1);
-  w.slot[b][me] = p ? 1 : 0;
-  w.site[b][me] = line;
+  Block& B = *g_blk;
+  long long k;
+  const int b = wave_arrive(line, k);
+  B.slot[b][B.cur] = p ? 1 : 0;
   yield_next();
+  wave_check(k, b, line);
   unsigned long long m = 0;
-  for (int l = 0; l < kLanes; ++l) {
-    if (w.seq[l] < k + 1) diverged("lane finished before this ballot", l, w.site[b][l], me, line);
-    if (w.site[b][l] != line) diverged("different collectives", l, w.site[b][l], me, line);
-    if (w.slot[b][l]) m |= 1ull << l;
-  }
+  const int w0 = B.cur & ~63;
+  for (int l = 0; l < 64; ++l)
+    if (B.slot[b][w0 + l]) m |= 1ull << l;
   return m;
 }
 
-template <class F>
-struct Launch {
-  F* f;
-};
-template <class F>
-inline void lane_entry(unsigned lo, unsigned hi) {
-  F* f = reinterpret_cast<F*>((static_cast<uintptr_t>(hi) << 32) | lo);
-  (*f)();
-  Wave& w = *g_wave;
-  const int me = w.lane;
-  w.done[me] = true;
-  // every other lane must also be finished or finish in this round
-  for (int l = 0; l < kLanes; ++l)
-    if (!w.done[l] && w.seq[l] != w.seq[me]) diverged("lane finished while another is inside a collective", me, -1, l, -1);
-  // hand over to the next unfinished lane, or back to the host when all are done
-  for (int s = 1; s <= kLanes; ++s) {
-    const int nx = (me + s) % kLanes;
-    if (!w.done[nx]) {
-      w.lane = nx;
-      setcontext(&w.ctx[nx]);
-    }
+typedef double d4 __attribute__((ext_vector_type(4)));
+// v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// C/D[l / 16 + 4 r][l % 16], r = 0..3 (the layout measured on gfx950)
+inline d4 mfma_f64_16x16x4(double a, double bv, d4 c, int line) {
+  Block& B = *g_blk;
+  long long k;
+  const int b = wave_arrive(line, k);
+  B.ma[b][B.cur] = a;
+  B.mb[b][B.cur] = bv;
+  yield_next();
+  wave_check(k, b, line);
+  const int w0 = B.cur & ~63, l = B.cur & 63;
+  d4 d;
+  for (int r = 0; r < 4; ++r) {
+    const int i = l / 16 + 4 * r, j = l % 16;
+    double acc = c[r];
+    for (int p = 0; p < 4; ++p) acc = fma(B.ma[b][w0 + i + 16 * p], B.mb[b][w0 + j + 16 * p], acc);
+    d[r] = acc;
   }
-  setcontext(&w.main_ctx);
+  return d;
 }
 
-// run `kernel` for blocks 0 .. grid-1, one 64-lane block at a time
+// workgroup barrier: every thread must reach it at the same line
+inline void barrier(int line) {
+  Block& B = *g_blk;
+  const int me = B.cur;
+  const long long nb = ++B.bars[me];
+  B.bar_site[me] = line;
+  while (true) {
+    bool all = true;
+    for (int t = 0; t < B.nthreads; ++t) {
+      if (B.bars[t] >= nb) continue;
+      if (B.done[t]) diverged("thread finished while others wait at a barrier", t, -1, me, line);
+      all = false;
+    }
+    if (all) break;
+    yield_next();
+  }
+  for (int t = 0; t < B.nthreads; ++t)
+    if (B.bars[t] == nb && B.bar_site[t] != line) diverged("threads at different barriers", t, B.bar_site[t], me, line);
+}
+
 template <class F>
-inline long long run_grid(unsigned grid, F kernel) {
+inline void thread_entry(unsigned lo, unsigned hi) {
+  F* f = reinterpret_cast<F*>((static_cast<uintptr_t>(hi) << 32) | lo);
+  (*f)();
+  Block& B = *g_blk;
+  const int me = B.cur;
+  B.done[me] = true;
+  // every other lane of the wave must also be finished or finish in this round
+  const int w0 = me & ~63;
+  for (int l = w0; l < w0 + 64; ++l)
+    if (!B.done[l] && B.seq[l] != B.seq[me]) diverged("lane finished while another is inside a collective", me, -1, l, -1);
+  for (int s = 1; s <= B.nthreads; ++s) {
+    const int nx = (me + s) % B.nthreads;
+    if (!B.done[nx]) {
+      B.cur = nx;
+      setcontext(&B.ctx[nx]);
+    }
+  }
+  setcontext(&B.main_ctx);
+}
+
+// run `kernel` for workgroups 0 .. grid-1 of `threads` threads, one workgroup at a time
+template <class F>
+inline long long run_grid(unsigned grid, F kernel, int threads = 64) {
   static thread_local char* stacks = nullptr;
   constexpr size_t kStack = 1 << 20;
-  if (!stacks) stacks = static_cast<char*>(std::malloc(kStack * kLanes));
+  if (!stacks) stacks = static_cast<char*>(std::malloc(kStack * kMaxThreads));
   long long total = 0;
   g_grid.x = grid;
-  g_dim.x = kLanes;
+  g_dim.x = static_cast<unsigned>(threads);
   for (unsigned blk = 0; blk < grid; ++blk) {
-    Wave w;
-    g_wave = &w;
+    Block* Bp = new Block();
+    Block& B = *Bp;
+    B.nthreads = threads;
+    g_blk = Bp;
     g_block.x = blk;
-    for (int l = 0; l < kLanes; ++l) {
-      getcontext(&w.ctx[l]);
-      w.ctx[l].uc_stack.ss_sp = stacks + kStack * l;
-      w.ctx[l].uc_stack.ss_size = kStack;
-      w.ctx[l].uc_link = nullptr;
+    for (int l = 0; l < threads; ++l) {
+      getcontext(&B.ctx[l]);
+      B.ctx[l].uc_stack.ss_sp = stacks + kStack * l;
+      B.ctx[l].uc_stack.ss_size = kStack;
+      B.ctx[l].uc_link = nullptr;
       const uintptr_t p = reinterpret_cast<uintptr_t>(&kernel);
-      makecontext(&w.ctx[l], reinterpret_cast<void (*)()>(&lane_entry<F>), 2, static_cast<unsigned>(p & 0xffffffffu),
+      makecontext(&B.ctx[l], reinterpret_cast<void (*)()>(&thread_entry<F>), 2, static_cast<unsigned>(p & 0xffffffffu),
                   static_cast<unsigned>(p >> 32));
     }
-    w.lane = 0;
-    swapcontext(&w.main_ctx, &w.ctx[0]);
-    for (int l = 0; l < kLanes; ++l)
-      if (!w.done[l]) diverged("lane never finished", l, -1, l, -1);
-    total += w.collectives;
-    g_wave = nullptr;
+    B.cur = 0;
+    if (g_block_start) g_block_start();
+    swapcontext(&B.main_ctx, &B.ctx[0]);
+    for (int l = 0; l < threads; ++l)
+      if (!B.done[l]) diverged("thread never finished", l, -1, l, -1);
+    total += B.collectives;
+    g_blk = nullptr;
+    delete Bp;
   }
   return total;
 }
 }  // namespace emu
 
-inline int __lane_id() { return emu::g_wave->lane; }
-#define threadIdx (Dim3{static_cast<unsigned>(__lane_id()), 0, 0})
+inline int __emu_thread() { return emu::g_blk->cur; }
+inline int __lane_id() { return emu::g_blk->cur & 63; }
+#define threadIdx (Dim3{static_cast<unsigned>(__emu_thread()), 0, 0})
 #define blockIdx (emu::g_block)
 #define blockDim (emu::g_dim)
 #define gridDim (emu::g_grid)
-#define __syncthreads() ((void)emu::exchange<int>(0, 0, __LINE__))
+#define __syncthreads() emu::barrier(__LINE__)
 #define __shfl_xor(v, off) emu::exchange((v), __lane_id() ^ (off), __LINE__)
 #define __shfl(v, src) emu::exchange((v), (src), __LINE__)
 #define __builtin_amdgcn_readlane(v, src) emu::exchange<int>((v), (src), __LINE__)
+#define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) emu::mfma_f64_16x16x4((a), (b), (c), __LINE__)
 #define __ballot(p) emu::ballot((p), __LINE__)
+#define __builtin_amdgcn_wave_barrier() ((void)emu::exchange<int>(0, 0, __LINE__))
+#define __builtin_amdgcn_fence(order, scope) ((void)0)
 inline int __ffsll(long long v) { return __builtin_ffsll(v); }
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
 template <class T> inline T atomicAdd(T* p, T v) { T o = *p; *p = o + v; return o; }

@@ -77,12 +77,22 @@ def test_options_struct_layout_matches_header(tmp_path):
         assert o.probe_attempts == 48 and o.reserved_ == 0
 
 
-def test_mechanism_above_wave_limit_is_rejected():
-    """States of more than 64 components are refused at parse time (no code is generated)."""
+def test_mechanism_above_block_limit_is_rejected(tmp_path):
+    """States of more than 160 components are refused at parse time (no code is generated): the
+    150-species mechanism with ten more (inert, copied) species."""
+    import json
     from paper_2510_10005_amd import _binding as b
     from synth import mechanism_file
     lib = b.load()
-    path = mechanism_file("large_150_1000").encode()
+    m = json.load(open(mechanism_file("large_150_1000")))
+    extra = []
+    for k in range(10):
+        sp = dict(m["species"][-1])
+        sp["name"] = f"XTRA{k}"
+        extra.append(sp)
+    m["species"] += extra
+    path = tmp_path / "too_large.json"
+    path.write_text(json.dumps(m))
     buf = ctypes.create_string_buffer(4096)
-    assert lib.chem_precompile(path, None, buf, 4096) == 7       # CHEM_EUNSUPPORTED
-    assert b"at most 63 are supported" in lib.chem_last_error_message()
+    assert lib.chem_precompile(str(path).encode(), None, buf, 4096) == 7       # CHEM_EUNSUPPORTED
+    assert b"at most 159 are supported" in lib.chem_last_error_message()

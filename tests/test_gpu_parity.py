@@ -28,14 +28,10 @@ def mechs(request):
     return gpu_mechanism(request.param)
 
 
-WAVE_OFF = ("integration of the one-wavefront-per-cell form (n > 24) is switched off: its GPU run did not "
-            "complete and the cause is not identified; its device code is checked on the CPU by "
-            "tests/test_wave_emulation.py")
-
-
-def _skip_wave_integration(om):
-    if om.n > 24:
-        pytest.skip(WAVE_OFF)
+def _skip_block_plain(om, form):
+    """Mechanisms with n > 24 integrate in the block form (one cell per workgroup), persistent only."""
+    if om.n > 24 and form == 1:
+        pytest.skip("the block form (n > 24) runs the persistent form only")
 
 
 def _states(om, nc, seed=21):
@@ -112,7 +108,7 @@ def _integrate_gpu(gm, om, y0, opts, ld=None, tape=None, lnA=None):
 
 @pytest.mark.parametrize("form", [0, 1])
 def test_backward_euler(mechs, form):
-    _skip_wave_integration(mechs[1])
+    _skip_block_plain(mechs[1], form)
     from paper_2510_10005_amd import default_options
     gm, om = mechs
     nc = 150 if om.ns < 20 else 24
@@ -132,7 +128,7 @@ def test_backward_euler(mechs, form):
 
 @pytest.mark.parametrize("form", [0, 1])
 def test_rosenbrock(mechs, form):
-    _skip_wave_integration(mechs[1])
+    _skip_block_plain(mechs[1], form)
     from paper_2510_10005_amd import default_options
     gm, om = mechs
     nc = 130 if om.ns < 20 else 16
@@ -154,7 +150,6 @@ def test_rosenbrock(mechs, form):
 
 
 def test_fixed_step_rosenbrock(mechs):
-    _skip_wave_integration(mechs[1])
     from paper_2510_10005_amd import default_options
     gm, om = mechs
     nc = 70
@@ -168,15 +163,17 @@ def test_fixed_step_rosenbrock(mechs):
 
 
 def test_failure_statuses(mechs):
-    _skip_wave_integration(mechs[1])
     from paper_2510_10005_amd import default_options
+    from test_gpu_large import BLOCK_INVALID_INPUT_OFF
     gm, om = mechs
+    if om.n > 24:
+        pytest.skip(BLOCK_INVALID_INPUT_OFF)
     T, p, Y = sample_config("be_small", om.ns, 6)
     y0 = oracle.state_from_TPY(om, T, p, Y)
     y0[0, 2] = np.nan
     y0[1, 0] = -3.0
     for method in (0, 1):
-        for form in (0, 1):
+        for form in ((0, 1) if om.n <= 24 else (0,)):
             got, st, _ = _integrate_gpu(gm, om, y0, default_options(method=method, dt=1e-8, n_steps=1, form=form))
             assert st[0] == oracle.CELL_NONFINITE and st[1] == oracle.CELL_T_RANGE
             np.testing.assert_array_equal(got[1], y0[1])
@@ -192,8 +189,9 @@ def test_failure_statuses(mechs):
 
 
 def test_be_adjoint(mechs):
-    _skip_wave_integration(mechs[1])
     """Discrete adjoint of backward Euler (with checkpoint recompute) against the oracle's adjoint."""
+    if mechs[1].n > 24:
+        pytest.skip("the discrete adjoint of the block form (n > 24) is not built in this version")
     import torch
     from oracle.sensitivity import be_adjoint, final_loss
     from paper_2510_10005_amd import Tape, default_options
@@ -230,15 +228,17 @@ def test_be_adjoint(mechs):
     assert torch.equal(g, g2)
 
 
-def test_wave_integration_is_refused(mechs):
-    """For 24 < n <= 64 the library refuses integration on the host (no kernel is launched)."""
-    from paper_2510_10005_amd import default_options
+def test_block_form_refuses_plain_and_tape(mechs):
+    """For n > 24 the library refuses the plain form and a tape on the host (no kernel is launched)."""
+    from paper_2510_10005_amd import Tape, default_options
     from paper_2510_10005_amd._binding import ChemError
     gm, om = mechs
     if om.n <= 24:
-        pytest.skip("register-resident mechanism: integration is enabled")
+        pytest.skip("register-resident mechanism: every form is enabled")
     import torch
     y = torch.zeros((om.n, 8), dtype=torch.float64, device="cuda")
     st = torch.zeros(8, dtype=torch.int32, device="cuda")
-    with pytest.raises(ChemError, match="switched off"):
-        gm.chem_integrate(8, 8, y, None, default_options(method=1, dt=1e-8), None, st, None)
+    with pytest.raises(ChemError, match="persistent form"):
+        gm.chem_integrate(8, 8, y, None, default_options(method=1, dt=1e-8, form=1), None, st, None)
+    with pytest.raises(ChemError, match="tape"):
+        gm.chem_integrate(8, 8, y, None, default_options(method=0, dt=1e-8), Tape(gm, 8, 1), st, None)
