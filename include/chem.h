@@ -261,6 +261,21 @@ chem_err chem_integrate(const chem_mech* mech, int64_t n_cells, int64_t ld, doub
                         const double* lnA, const chem_integrator_opts* opts, chem_tape* tape,
                         int32_t* status, int32_t* counters, void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): chem_integrate without a tape, persistent form only, with
+ * every library workspace (work-queue counter, probe/resume schedule, parked cells' state and
+ * order, and the counters when counters is NULL) taken from a device array of 48 MiB + 4352 B
+ * that the library holds per GPU until the process ends; it calls no hipMalloc, hipFree or other
+ * allocating routine.  Limits: n_cells <= 2^20 and, with counters NULL, ld <= 2^20
+ * (CHEM_EINVAL otherwise); CHEM_FLAG_CHECK_CELLS is refused.  The array is shared by every
+ * mechanism and stream on a GPU and keeps the last call's contents (what must start at zero is
+ * cleared by each call): calls that overlap in time on one GPU race, so the caller must order
+ * them (one stream, or events).  Same arguments, results and per-cell statuses as chem_integrate.
+ */
+chem_err chem_integrate_noalloc(const chem_mech* mech, int64_t n_cells, int64_t ld, double* y, const double* lnA,
+                                const chem_integrator_opts* opts, int32_t* status, int32_t* counters, void* stream);
+
 /* Tape for the backward-Euler discrete adjoint: the state is checkpointed every
  * checkpoint_every steps; the backward pass recomputes each segment from its checkpoint. */
 chem_err chem_tape_create(const chem_mech* mech, int64_t n_cells, int checkpoint_every, chem_tape** out);

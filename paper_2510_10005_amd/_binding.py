@@ -30,7 +30,7 @@ EXPORTED = [
     "chem_default_lnA", "chem_thermo", "chem_source_terms", "chem_jacobian", "chem_state_from_TPY",
     "chem_mass_fractions", "chem_state_from_TPY_vjp", "chem_mass_fractions_vjp", "chem_integrate",
     "chem_tape_create", "chem_tape_create_ros2", "chem_tape_free", "chem_integrate_adjoint", "chem_set_launch",
-    "chem_get_launch", "chem_autotune", "chem_T_from_energy", "chem_cfd_source",
+    "chem_get_launch", "chem_autotune", "chem_T_from_energy", "chem_cfd_source", "chem_integrate_noalloc",
 ]
 
 
@@ -97,6 +97,7 @@ def load():
     lib.chem_state_from_TPY_vjp.argtypes = [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P]
     lib.chem_mass_fractions_vjp.argtypes = [_P, _I64, _I64, _P, _P, _P, _P, _P]
     lib.chem_integrate.argtypes = [_P, _I64, _I64, _P, _P, ctypes.POINTER(IntegratorOptions), _P, _P, _P, _P]
+    lib.chem_integrate_noalloc.argtypes = [_P, _I64, _I64, _P, _P, ctypes.POINTER(IntegratorOptions), _P, _P, _P]
     lib.chem_tape_create.argtypes = [_P, _I64, _I, ctypes.POINTER(_P)]
     lib.chem_tape_create_ros2.argtypes = [_P, _I64, _I, _I, ctypes.POINTER(_P)]
     lib.chem_tape_free.argtypes = [_P]
@@ -216,6 +217,10 @@ class Mechanism:
         _check(self.lib.chem_integrate(self.handle, n, ld, _ptr(y), _ptr(lnA), ctypes.byref(opts),
                                        tape.handle if tape is not None else None, _ptr(status), _ptr(counters),
                                        _stream()), "chem_integrate")
+
+    def chem_integrate_noalloc(self, n, ld, y, lnA, opts, status, counters):
+        _check(self.lib.chem_integrate_noalloc(self.handle, n, ld, _ptr(y), _ptr(lnA), ctypes.byref(opts),
+                                               _ptr(status), _ptr(counters), _stream()), "chem_integrate_noalloc")
 
     def chem_integrate_adjoint(self, tape, lnA, dLdyN, dLdy0, dLdlnA):
         _check(self.lib.chem_integrate_adjoint(self.handle, tape.handle, _ptr(lnA), _ptr(dLdyN), _ptr(dLdy0),

@@ -21,11 +21,24 @@ KERNEL_CACHE = os.path.join(ROOT, "_build", "kernels")
 SOURCES = ["chem.cpp", "codegen.cpp", "mechanism.cpp"]
 
 
+# HIP flags of device code compiled into the library itself (the allocation-free entry point's
+# scratch array); packed FP32 instructions are disabled in every HIP build of this project
+DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
 def build_library(verbose: bool = True) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    obj_dir = os.path.join(ROOT, "_build", "obj")
+    os.makedirs(obj_dir, exist_ok=True)
+    dev_obj = os.path.join(obj_dir, "noalloc.o")
+    cmd = [hipcc, "-O2", "-std=c++17", "-fPIC", "-Wall", "-x", "hip", *DEVICE_FLAGS, "-I", INCLUDE, "-I", CSRC,
+           "-c", os.path.join(CSRC, "noalloc.hip"), "-o", dev_obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
     cmd = [hipcc, "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-Wall", "-Wno-unused-function",
            "-I", INCLUDE, "-I", CSRC, "-o", LIB + ".tmp"]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES]
+    cmd += [os.path.join(CSRC, s) for s in SOURCES] + ["-x", "none", dev_obj]
     cmd += ["-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)

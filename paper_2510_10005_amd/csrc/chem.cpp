@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "mechanism.hpp"
+#include "noalloc.hpp"
 
 namespace {
 
@@ -289,6 +290,7 @@ struct chem_mech {
   hipEvent_t fence = nullptr;
   hipStream_t fence_stream = nullptr;
   bool fence_set = false;
+  unsigned char* scratch = nullptr;  // this device's scratch array of chem_integrate_noalloc
   std::mutex mu;
   ~chem_mech() {
     if (fence) (void)hipEventDestroy(fence);
@@ -559,6 +561,11 @@ chem_err chem_load_mechanism(const char* path, const char* cache_dir, chem_mech*
   if ((e = M->running.ensure(64 * sizeof(unsigned int)))) return e;
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&M->running_host), sizeof(unsigned int), hipHostMallocDefault));
   HIP_TRY(hipEventCreateWithFlags(&M->fence, hipEventDisableTiming));
+  {
+    void* sp = nullptr;
+    HIP_TRY(chem_noalloc::scratch_address(M->device, &sp));
+    M->scratch = static_cast<unsigned char*>(sp);
+  }
   *out = M.release();
   return CHEM_OK;
 }
@@ -759,6 +766,28 @@ chem_err chem_integrate(const chem_mech* Mc, int64_t n, int64_t ld, double* y, c
   return integrate_impl(const_cast<chem_mech*>(Mc), n, ld, y, lnA, opts, tape, status, counters, stream, nullptr);
 }
 
+chem_err chem_integrate_noalloc(const chem_mech* Mc, int64_t n, int64_t ld, double* y, const double* lnA,
+                                const chem_integrator_opts* opts, int32_t* status, int32_t* counters, void* stream) {
+  chem_mech* M = const_cast<chem_mech*>(Mc);
+  if (!M || !opts) return fail(CHEM_EINVAL, "null argument");
+  if (opts->form != CHEM_PERSISTENT) return fail(CHEM_EINVAL, "chem_integrate_noalloc runs the persistent form only");
+  if (opts->flags & CHEM_FLAG_CHECK_CELLS)
+    return fail(CHEM_EINVAL, "CHEM_FLAG_CHECK_CELLS is not available in chem_integrate_noalloc");
+  if (n > chem_noalloc::kMaxCells)
+    return fail(CHEM_EINVAL, "chem_integrate_noalloc takes at most " + std::to_string(chem_noalloc::kMaxCells) +
+                                 " cells per call (got " + std::to_string(n) + ")");
+  if (!counters && ld > chem_noalloc::kMaxCells)
+    return fail(CHEM_EINVAL, "chem_integrate_noalloc without a counters array needs ld <= " +
+                                 std::to_string(chem_noalloc::kMaxCells));
+  if (!M->scratch) return fail(CHEM_EDEVICE, "the scratch array of this device is not resolved");
+  FixedWorkspace fw{reinterpret_cast<uint64_t*>(M->scratch + chem_noalloc::kQueueOff),
+                    reinterpret_cast<unsigned int*>(M->scratch + chem_noalloc::kSchedOff),
+                    reinterpret_cast<double*>(M->scratch + chem_noalloc::kWstOff),
+                    reinterpret_cast<int*>(M->scratch + chem_noalloc::kOrderOff),
+                    reinterpret_cast<int*>(M->scratch + chem_noalloc::kCountersOff), chem_noalloc::kMaxCells};
+  return integrate_impl(M, n, ld, y, lnA, opts, nullptr, status, counters, stream, &fw);
+}
+
 }  // extern "C"
 
 namespace {
@@ -777,6 +806,8 @@ chem_err integrate_impl(chem_mech* M, int64_t n, int64_t ld, double* y, const do
       return fail(CHEM_EUNSUPPORTED, "mechanisms with n > 24 integrate in the persistent form");
     if (tape && !M->fn[K_BE_ADJOINT])
       return fail(CHEM_EUNSUPPORTED, "no adjoint tape for mechanisms with n > 24 in this version");
+    if (fw && M->np > 64)
+      return fail(CHEM_EUNSUPPORTED, "chem_integrate_noalloc covers mechanisms with n <= 64");
   }
   if (persistent_only(opts->method)) {
     if (opts->form != CHEM_PERSISTENT)
