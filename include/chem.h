@@ -174,8 +174,9 @@ const char* chem_last_error_message(void);
  * one cell per 256-thread workgroup with the species, reactions and matrix rows spread over the
  * threads (constants in generated tables) and the iteration matrix factored by a pivoted LU whose
  * updates run on the FP64 matrix cores (Section 3.4, direct solver).  In the block form
- * chem_integrate and chem_autotune serve CHEM_BE and CHEM_ROS2 in the persistent form (the plain
- * form, the other methods and adjoint tapes return CHEM_EUNSUPPORTED); its Jacobian API kernel runs
+ * chem_integrate and chem_autotune serve CHEM_BE and CHEM_ROS2 in the persistent form, with
+ * backward-Euler adjoint tapes (the plain form, the other methods and Rosenbrock tapes return
+ * CHEM_EUNSUPPORTED); its Jacobian API kernel runs
  * one cell per 64-lane wavefront for n <= 64.  n > 160 is rejected with CHEM_EUNSUPPORTED.
  * On success *out owns the mechanism; release it with chem_free_mechanism.
  */
@@ -276,8 +277,9 @@ chem_err chem_integrate(const chem_mech* mech, int64_t n_cells, int64_t ld, doub
 chem_err chem_integrate_noalloc(const chem_mech* mech, int64_t n_cells, int64_t ld, double* y, const double* lnA,
                                 const chem_integrator_opts* opts, int32_t* status, int32_t* counters, void* stream);
 
-/* Tape for the backward-Euler discrete adjoint: the state is checkpointed every
- * checkpoint_every steps; the backward pass recomputes each segment from its checkpoint. */
+/* Tape for the backward-Euler discrete adjoint (every n <= 160): the state is checkpointed every
+ * checkpoint_every steps; the backward pass recomputes each segment from its checkpoint.  In the
+ * block form (n > 24) the backward pass maps cells statically to workgroups, one cell at a time. */
 chem_err chem_tape_create(const chem_mech* mech, int64_t n_cells, int checkpoint_every, chem_tape** out);
 
 /* Tape for the discrete adjoint of the two-stage Rosenbrock method (Appendix A.3), n <= 24 only

@@ -799,13 +799,14 @@ chem_err integrate_impl(chem_mech* M, int64_t n, int64_t ld, double* y, const do
   if (chem_err e = check_cells(M, n, ld)) return e;
   if (chem_err e = validate_opts(opts)) return e;
   if (M->wave) {
-    // the block form (n > 24): backward Euler and Rosenbrock, persistent form, no tape yet
+    // the block form (n > 24): backward Euler and Rosenbrock, persistent form; adjoint tapes for
+    // backward Euler only
     if (opts->method != CHEM_BE && opts->method != CHEM_ROS2)
       return fail(CHEM_EUNSUPPORTED, std::string(method_name(opts->method)) + " is implemented for n <= 24");
     if (opts->form != CHEM_PERSISTENT)
       return fail(CHEM_EUNSUPPORTED, "mechanisms with n > 24 integrate in the persistent form");
-    if (tape && !M->fn[K_BE_ADJOINT])
-      return fail(CHEM_EUNSUPPORTED, "no adjoint tape for mechanisms with n > 24 in this version");
+    if (tape && (opts->method != CHEM_BE || !M->fn[K_BE_ADJOINT]))
+      return fail(CHEM_EUNSUPPORTED, "mechanisms with n > 24 record adjoint tapes for backward Euler only");
     if (fw && M->np > 64)
       return fail(CHEM_EUNSUPPORTED, "chem_integrate_noalloc covers mechanisms with n <= 64");
   }
@@ -1040,7 +1041,8 @@ chem_err chem_integrate_adjoint(const chem_mech* Mc, chem_tape* tape, const doub
   chem_mech* M = const_cast<chem_mech*>(Mc);
   if (!M || !tape || !dLdyN || !dLdy0 || !dLdlnA) return fail(CHEM_EINVAL, "null argument");
   if (tape->mech != M) return fail(CHEM_EINVAL, "tape belongs to another mechanism");
-  if (M->wave && !M->fn[K_BE_ADJOINT]) return fail(CHEM_EUNSUPPORTED, "no adjoint for mechanisms with n > 24 in this version");
+  if (M->wave && (tape->method != CHEM_BE || !M->fn[K_BE_ADJOINT]))
+    return fail(CHEM_EUNSUPPORTED, "mechanisms with n > 24 have the backward-Euler adjoint only");
   if (!tape->recorded) return fail(CHEM_EINVAL, "tape holds no recorded forward run");
   std::lock_guard<std::mutex> lock(M->mu);
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1050,11 +1052,11 @@ chem_err chem_integrate_adjoint(const chem_mech* Mc, chem_tape* tape, const doub
   const double* la = lnA ? lnA : M->lnA_default.as<double>();
   const int NY = M->m.n(), NR = std::max(1, M->m.nr());
   if (tape->method == CHEM_ROS2) return ros2_adjoint(M, tape, la, dLdyN, dLdy0, dLdlnA, s);
-  const int block = M->wave ? 64 : 256;
+  const int block = 256;
   const unsigned cap = static_cast<unsigned>(occupancy_blocks(M, K_BE_ADJOINT, block) * M->num_cu);
   const unsigned grid = std::max(1u, std::min(M->wave ? static_cast<unsigned>(std::min<int64_t>(n, 1 << 30))
                                                       : blocks_for(n, block), cap));
-  // state slots of the segment recompute: one per lane, or one per wave in the wave form
+  // state slots of the segment recompute: one per lane, or one per workgroup in the block form
   int64_t total = M->wave ? static_cast<int64_t>(grid) : static_cast<int64_t>(grid) * block;
   chem_err e;
   const int K = tape->opts.ckpt_every;
@@ -1067,6 +1069,10 @@ chem_err chem_integrate_adjoint(const chem_mech* Mc, chem_tape* tape, const doub
     if ((e = M->gws.ensure(sizeof(double) * static_cast<size_t>(NR) * total))) return e;
     ws = M->ws.as<double>();
     gws = M->gws.as<double>();
+  } else if (M->wave && M->np > 64) {
+    // block form with the factors in device memory: one padded matrix per workgroup
+    if ((e = M->ws.ensure(sizeof(double) * static_cast<size_t>(M->np) * M->np * grid))) return e;
+    ws = M->ws.as<double>();
   }
   DevChemOpts o = tape->opts;
   const int* st = tape->status.as<int>();

@@ -3,6 +3,9 @@
 // Usage:
 //   block_driver be|ros2|ros2p n ld dt n_steps in.bin out.bin [grid]   (ros2p: probe/resume schedule)
 //     in.bin: state [NY][ld] then ln A [NR]; out.bin: state, status [ld], counters [3][ld]
+//   block_driver adj n ld dt n_steps K in.bin out.bin [grid]   (backward Euler with a tape, then its adjoint)
+//     in.bin: state [NY][ld], ln A [NR], dL/dy_N [NY][ld]; out.bin: state, status [ld], dL/dy0 [NY][ld],
+//     dL/dlnA [NR] (workgroup partials summed in workgroup order)
 //   block_driver src|jac n ld in.bin out.bin          (API kernels of mechanisms with n > 64)
 //     in.bin: state [NY][ld] then ln A [NR]; out.bin: sources [NY][ld] then (jac) [n][NY][NY]
 //   block_driver lu in.bin out.bin
@@ -85,6 +88,48 @@ int main(int argc, char** argv) {
     fwrite(J.data(), 8, J.size(), f);
     fclose(f);
     return 0;
+#endif
+  }
+  if (!strcmp(which, "adj")) {
+#if CHEM_IN_GROUP(3)
+    if (argc < 9) return 2;
+    const double dt = atof(argv[4]);
+    const int n_steps = atoi(argv[5]), K = atoi(argv[6]);
+    const unsigned grid = argc > 9 ? (unsigned)atoi(argv[9]) : 2u;
+    std::vector<double> in((size_t)2 * NY * ld + NR);
+    if (!read_all(argv[7], in)) return 4;
+    std::vector<double> y(in.begin(), in.begin() + (size_t)NY * ld);
+    std::vector<double> lnA(in.begin() + (size_t)NY * ld, in.begin() + (size_t)NY * ld + NR);
+    std::vector<double> lamN(in.begin() + (size_t)NY * ld + NR, in.end());
+    std::vector<double> ws((size_t)grid * BK_NP * BK_NP, 0.0), ckpt((size_t)(n_steps / K + 1) * NY * ld, 0.0);
+    std::vector<double> seg((size_t)grid * K * NY, 0.0), gpart((size_t)grid * NR, 0.0), lam0((size_t)NY * ld, 0.0);
+    std::vector<unsigned short> nsub((size_t)n_steps * ld, 0);
+    std::vector<int> status(ld, -7), counters(3 * ld, 0);
+    unsigned long long queue = 0;
+    ChemOpts o{};
+    o.dt = dt; o.rtol = 1e-6; o.atol = 1e-10; o.h_min = 1e-20; o.newton_rtol = 1e-10; o.newton_atol_T = 1e-8;
+    o.newton_atol_Y = 1e-14; o.n_steps = n_steps; o.max_steps = 100000; o.newton_max = 10;
+    o.halving_max_depth = 8; o.energy = 0; o.ckpt_every = K;
+    emu::run_grid(grid, [&] {
+      chem_k_be_persistent(n, ld, y.data(), lnA.data(), o, status.data(), counters.data(), &queue, ws.data(), 0,
+                           ckpt.data(), nsub.data());
+    }, BK_T);
+    emu::run_grid(grid, [&] {
+      chem_k_be_adjoint(n, ld, lnA.data(), o, status.data(), ckpt.data(), nsub.data(), lamN.data(), lam0.data(),
+                        gpart.data(), seg.data(), grid, ws.data(), grid, nullptr);
+    }, BK_T);
+    std::vector<double> g(NR, 0.0);
+    for (unsigned b = 0; b < grid; ++b)
+      for (int j = 0; j < NR; ++j) g[j] += gpart[(size_t)b * NR + j];
+    FILE* f = fopen(argv[8], "wb");
+    fwrite(y.data(), 8, y.size(), f);
+    fwrite(status.data(), 4, ld, f);
+    fwrite(lam0.data(), 8, lam0.size(), f);
+    fwrite(g.data(), 8, g.size(), f);
+    fclose(f);
+    return 0;
+#else
+    return 5;
 #endif
   }
   if (argc < 8) return 2;

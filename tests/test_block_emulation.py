@@ -17,7 +17,8 @@ Rosenbrock method against the oracle (equal step sequences, states within 1e-8) 
 mechanism (also the 24-cell, 6 x 1e-8 s configuration, several workgroups on one queue) and on the
 30-species SRI/P-log mechanism at both P-log pressure intervals; the source-term and Jacobian
 kernels of the 150-species mechanism against the oracle (1e-12 of the term magnitudes) and its
-fixed-step Rosenbrock integration.
+fixed-step Rosenbrock integration; the backward-Euler discrete adjoint (tape, segment recompute,
+halved steps) of all three mechanisms against the oracle's reverse sweep (1e-6).
 """
 
 import os
@@ -189,3 +190,46 @@ def test_block_rosenbrock_150_species(generator, tmp_path_factory):
     np.testing.assert_array_equal(st, ref["status"])
     np.testing.assert_array_equal(cnt[0], ref["accepted"])
     assert integrated_state_error(om, y, ref["y"]).max() <= 1e-8
+
+
+@pytest.mark.parametrize("name,step,nc,cfg", [("ch4like_53_325", 1e-6, 3, "be_small"), ("mix_30_90", 1e-3, 3, "be_small"),
+                                              ("large_150_1000", 1e-11, 1, "ros2_large")])
+def test_block_be_adjoint_matches_oracle(generator, tmp_path_factory, name, step, nc, cfg):
+    """Backward Euler with a tape (checkpoints every 2 steps, 3 steps: for the two smaller mechanisms
+    a halved step and a partial last segment), then the block-form discrete adjoint against the
+    oracle's reverse sweep along the oracle's recorded (sub)steps; the 150-species mechanism keeps
+    its factors in the device workspace."""
+    from oracle.sensitivity import be_adjoint, final_loss
+    from synth.states import loss_weights
+    exe, d, om = _driver(generator, tmp_path_factory, name)
+    ld, grid = nc + 2, 2
+    dt, n_steps, K = 3 * step, 3, 2
+    T, p, Y = sample_config(cfg, om.ns, nc)
+    if any(rx.kind == "plog" for rx in om.reactions):
+        p = np.geomspace(2e4, 2e6, nc)
+    y0 = oracle.state_from_TPY(om, T, p, Y)
+    ref = oracle.integrate_be(om, y0, dt, n_steps, record=True)
+    if om.ns < 100:
+        assert max(len(t) for t in ref["trajectory"]) > n_steps  # at least one halved step
+    _, lamN = final_loss(om, ref["y"], loss_weights(nc, om.ns))
+    ys, ls = np.zeros((om.n, ld)), np.zeros((om.n, ld))
+    ys[:, :nc], ls[:, :nc] = y0.T, lamN.T
+    fin, fout = os.path.join(d, "adj_in.bin"), os.path.join(d, "adj_out.bin")
+    with open(fin, "wb") as f:
+        f.write(ys.astype("<f8").tobytes())
+        f.write(np.asarray(om.lnA_default, "<f8").tobytes())
+        f.write(ls.astype("<f8").tobytes())
+    _run([exe, "adj", str(nc), str(ld), repr(dt), str(n_steps), str(K), fin, fout, str(grid)])
+    raw = open(fout, "rb").read()
+    k = 8 * om.n * ld
+    y = np.frombuffer(raw[:k], "<f8").reshape(om.n, ld)[:, :nc].T
+    st = np.frombuffer(raw[k:k + 4 * ld], "<i4")[:nc]
+    lam0 = np.frombuffer(raw[k + 4 * ld:2 * k + 4 * ld], "<f8").reshape(om.n, ld)[:, :nc].T
+    g = np.frombuffer(raw[2 * k + 4 * ld:], "<f8")
+    np.testing.assert_array_equal(st, ref["status"])
+    assert integrated_state_error(om, y, ref["y"]).max() <= 1e-8
+    lam0_ref, g_ref = be_adjoint(om, lamN, ref["trajectory"])
+    scale = np.abs(lam0_ref).max(axis=0, keepdims=True)
+    assert (np.abs(lam0 - lam0_ref) / np.where(scale > 0, scale, 1.0)).max() <= 1e-6
+    gs = g_ref.sum(axis=0)
+    assert (np.abs(g - gs) / np.abs(gs).max()).max() <= 1e-6

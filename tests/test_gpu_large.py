@@ -113,3 +113,35 @@ def test_failure_statuses_150(large):
         got, st, _ = _integrate(gm, om, y0, default_options(method=method, dt=1e-13, n_steps=1), 4)
         assert st[0] == oracle.CELL_NONFINITE and st[1] == oracle.CELL_T_RANGE
         np.testing.assert_array_equal(got[1], y0[1])
+
+
+def test_backward_euler_adjoint_150(large):
+    """Discrete adjoint of backward Euler for n = 151 (factors in the device workspace) against the
+    oracle's reverse sweep: 4 cells, 3 steps of 1e-11 s, checkpoints every 2 steps."""
+    import torch
+    from oracle.sensitivity import be_adjoint, final_loss
+    from paper_2510_10005_amd import Tape, default_options
+    from synth.states import loss_weights
+    gm, om = large
+    nc, dt, n_steps = 4, 3e-11, 3
+    T, p, Y = sample_config("ros2_large", om.ns, nc)
+    y0 = oracle.state_from_TPY(om, T, p, Y)
+    ref = oracle.integrate_be(om, y0, dt, n_steps, record=True)
+    _, lamN = final_loss(om, ref["y"], loss_weights(nc, om.ns))
+    lam0_ref, g_ref = be_adjoint(om, lamN, ref["trajectory"])
+    tape = Tape(gm, nc, 2)
+    yd = dev_soa(y0, nc)
+    st = torch.full((nc,), -7, dtype=torch.int32, device="cuda")
+    gm.chem_integrate(nc, nc, yd, None, default_options(method=0, dt=dt, n_steps=n_steps), tape, st, None)
+    np.testing.assert_array_equal(st.cpu().numpy(), ref["status"])
+    out = empty(om.n, nc)
+    g = torch.zeros(om.nr, dtype=torch.float64, device="cuda")
+    gm.chem_integrate_adjoint(tape, None, dev_soa(lamN, nc), out, g)
+    torch.cuda.synchronize()
+    lam0 = host_aos(out, nc)
+    scale = np.abs(lam0_ref).max(axis=0, keepdims=True)
+    e0 = np.abs(lam0 - lam0_ref) / np.where(scale > 0, scale, 1.0)
+    gs = g_ref.sum(axis=0)
+    eg = np.abs(g.cpu().numpy() - gs) / np.abs(gs).max()
+    print(f"[gpu] 150 species BE adjoint: dL/dy0 {e0.max():.2e}, dL/dlnA {eg.max():.2e}", flush=True)
+    assert e0.max() <= 1e-6 and eg.max() <= 1e-6

@@ -190,8 +190,6 @@ def test_failure_statuses(mechs):
 
 def test_be_adjoint(mechs):
     """Discrete adjoint of backward Euler (with checkpoint recompute) against the oracle's adjoint."""
-    if mechs[1].n > 24:
-        pytest.skip("the discrete adjoint of the block form (n > 24) is not built in this version")
     import torch
     from oracle.sensitivity import be_adjoint, final_loss
     from paper_2510_10005_amd import Tape, default_options
@@ -229,7 +227,8 @@ def test_be_adjoint(mechs):
 
 
 def test_block_form_refuses_plain_and_tape(mechs):
-    """For n > 24 the library refuses the plain form and a tape on the host (no kernel is launched)."""
+    """For n > 24 the library refuses the plain form and a Rosenbrock tape on the host (no kernel is
+    launched)."""
     from paper_2510_10005_amd import Tape, default_options
     from paper_2510_10005_amd._binding import ChemError
     gm, om = mechs
@@ -241,4 +240,5 @@ def test_block_form_refuses_plain_and_tape(mechs):
     with pytest.raises(ChemError, match="persistent form"):
         gm.chem_integrate(8, 8, y, None, default_options(method=1, dt=1e-8, form=1), None, st, None)
     with pytest.raises(ChemError, match="tape"):
-        gm.chem_integrate(8, 8, y, None, default_options(method=0, dt=1e-8), Tape(gm, 8, 1), st, None)
+        gm.chem_integrate(8, 8, y, None, default_options(method=1, dt=1e-8), Tape(gm, 8, 1, method=1, max_steps=16),
+                          st, None)
