@@ -39,7 +39,10 @@ static const char* kBlock =
 static int block_part_rows(int n, int nr, int md) {
   const int np = (n + 15) / 16 * 16, js = np + 1;
   if (np <= 64) return np;
-  const long fixed = 8L * (13L * np + 16 + static_cast<long>(nr) * (3 + md) + 10L * np + 8) + 4L * (2L * np + 8) + 64;
+  // LDS of the block form outside the Jacobian part for n_pad > 64 (the BkShared members): 14
+  // vectors, reductions, the records and the zero record, LU panel + pivot rows + 1/u_kk + T-row
+  // sums, scalars; ints: pivot step of each row, row of each step, scalars
+  const long fixed = 8L * (14L * np + 16 + static_cast<long>(nr + 1) * (3 + md) + 10L * np + 8) + 4L * (2L * np + 8) + 64;
   const long budget = 163840 - 1024 - fixed;
   long rows = budget / (8L * js);
   if (rows > np) rows = np;
@@ -308,32 +311,30 @@ static void emit_array(std::ostringstream& os, const char* type, const char* nam
   os << "};\n";
 }
 
-// returns the number of derivative-record species per reaction (WV_MD)
-static int emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
-  const int ns = m.ns(), nr = m.nr();
-  for (const Species& sp : m.species)
-    if (sp.poly)
-      throw std::runtime_error("polynomial-cp thermo is supported for mechanisms of at most 24 state components");
-  auto kind_of = [&](const Reaction& r) {
-    if (r.kind == RxKind::Elementary) return 0;
-    if (r.kind == RxKind::ThirdBody) return 1;
-    if (r.kind == RxKind::Plog) return 6;
-    if (r.sri) return 5;
-    if (!r.troe) return 2;
-    return r.troe_has_T2 ? 4 : 3;
-  };
-  std::vector<int> pos(nr);
-  for (int j = 0; j < nr; ++j) pos[j] = j;
+static int rate_kind(const Reaction& r) {
+  if (r.kind == RxKind::Elementary) return 0;
+  if (r.kind == RxKind::ThirdBody) return 1;
+  if (r.kind == RxKind::Plog) return 6;
+  if (r.sri) return 5;
+  if (!r.troe) return 2;
+  return r.troe_has_T2 ? 4 : 3;
+}
+
+// table position p -> reaction index (reactions grouped by rate kind, stable)
+static std::vector<int> table_positions(const Mechanism& m) {
+  std::vector<int> pos(m.nr());
+  for (int j = 0; j < m.nr(); ++j) pos[j] = j;
   std::stable_sort(pos.begin(), pos.end(),
-                   [&](int a, int b) { return kind_of(m.reactions[a]) < kind_of(m.reactions[b]); });
-  int MR = 1, MP = 1, MN = 1, ME = 1, MD = 1;
-  std::vector<std::vector<int>> dsp(nr);
-  for (int j = 0; j < nr; ++j) {
+                   [&](int a, int b) { return rate_kind(m.reactions[a]) < rate_kind(m.reactions[b]); });
+  return pos;
+}
+
+// species whose concentration a reaction's rate of progress depends on (its record lists dq/dC of
+// these, ascending): reactants, products of reversible reactions, enhanced colliders
+static std::vector<std::vector<int>> record_species(const Mechanism& m) {
+  std::vector<std::vector<int>> dsp(m.nr());
+  for (int j = 0; j < m.nr(); ++j) {
     const Reaction& r = m.reactions[j];
-    MR = std::max(MR, static_cast<int>(r.reactants.size()));
-    MP = std::max(MP, static_cast<int>(r.products.size()));
-    MN = std::max(MN, static_cast<int>(m.net(j).size()));
-    ME = std::max(ME, static_cast<int>(r.eff.size()));
     std::set<int> d;
     for (auto& p : r.reactants) d.insert(p.first);
     if (r.reversible)
@@ -341,7 +342,27 @@ static int emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
     if (r.kind != RxKind::Elementary)
       for (auto& e : r.eff) d.insert(e.first);
     dsp[j].assign(d.begin(), d.end());
-    MD = std::max(MD, static_cast<int>(d.size()));
+  }
+  return dsp;
+}
+
+// returns the number of derivative-record species per reaction (WV_MD)
+static int emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
+  const int ns = m.ns(), nr = m.nr();
+  for (const Species& sp : m.species)
+    if (sp.poly)
+      throw std::runtime_error("polynomial-cp thermo is supported for mechanisms of at most 24 state components");
+  auto kind_of = [&](const Reaction& r) { return rate_kind(r); };
+  const std::vector<int> pos = table_positions(m);
+  const std::vector<std::vector<int>> dsp = record_species(m);
+  int MR = 1, MP = 1, MN = 1, ME = 1, MD = 1;
+  for (int j = 0; j < nr; ++j) {
+    const Reaction& r = m.reactions[j];
+    MR = std::max(MR, static_cast<int>(r.reactants.size()));
+    MP = std::max(MP, static_cast<int>(r.products.size()));
+    MN = std::max(MN, static_cast<int>(m.net(j).size()));
+    ME = std::max(ME, static_cast<int>(r.eff.size()));
+    MD = std::max(MD, static_cast<int>(dsp[j].size()));
   }
   os << "#define WV_MR " << MR << "\n#define WV_MP " << MP << "\n#define WV_MN " << MN << "\n#define WV_ME " << ME
      << "\n#define WV_MD " << MD << "\n";
@@ -487,6 +508,98 @@ static int emit_wave_tables(std::ostringstream& os, const Mechanism& m) {
   emit_array(os, "double", "wv_nasa", nasa);
   emit_array(os, "double", "wv_tmid", tmid);
   return MD;
+}
+
+// Assembly tables of the block form, stored interleaved by thread (entry j of thread t at
+// j * 256 + t, every thread padded to the same count) so that a step of the loops over them is one
+// coalesced load for the workgroup and the loops have a uniform trip count.  Padding refers to the
+// zero record after the last reaction (position NR).
+//  * bk_sp_ops [BK_SPN][256]: for species t, its table positions p (ascending) with nonzero net
+//    coefficient: p << 8 | (nu & 255); the production rate, dS/dT and the default-efficiency
+//    third-body part of its row are sums over these.
+//  * bk_cs_ops [BK_CS_PARTS][BK_CSN][256]: the listed-species part of the Jacobian.  The species
+//    rows are assembled in parts of `part` matrix rows (row 1 + s for species s, parts starting at
+//    row 1); every structural nonzero (1 + s, 1 + k) of a part is one slot, the sum over the
+//    positions p (ascending) whose net coefficient of s is nonzero and whose record lists k of
+//    nu_sp times that record entry.  Slots go longest first to the least loaded thread; a thread's
+//    slots are consecutive runs of its ops.  Op: low word record index << 8 | (nu & 255), high
+//    word the slot's destination (row in the part << 16 | column) on its last term, else ~0.
+static void emit_block_jac_tables(std::ostringstream& os, const Mechanism& m, int part, int md) {
+  constexpr int kThreads = 256;   // the block form's workgroup size (BK_T)
+  const int ns = m.ns(), nr = m.nr(), n = m.n(), rec = 3 + md;
+  const std::vector<int> pos = table_positions(m);
+  const std::vector<std::vector<int>> dsp = record_species(m);
+  const int nparts = (n - 1 + part - 1) / part;
+  if (static_cast<long>(nr + 1) * rec >= (1L << 24)) throw std::runtime_error("reaction record table too large");
+  const unsigned zero_rec = static_cast<unsigned>(nr) * static_cast<unsigned>(rec);
+  // species sums
+  std::vector<std::vector<unsigned>> sp_ops(kThreads);
+  struct Slot {
+    int row, col;
+    std::vector<unsigned> terms;
+  };
+  std::vector<std::vector<Slot>> parts(nparts);
+  for (int s = 0; s < ns; ++s) {
+    std::vector<std::vector<unsigned>> by_col(ns);
+    for (int p = 0; p < nr; ++p) {
+      const int j = pos[p];
+      const auto nu = m.net(j);
+      const auto it = nu.find(s);
+      if (it == nu.end()) continue;
+      if (it->second < -128 || it->second > 127) throw std::runtime_error("net coefficient out of range");
+      const unsigned c = static_cast<unsigned>(it->second & 255);
+      sp_ops[s].push_back((static_cast<unsigned>(p) << 8) | c);
+      for (size_t d = 0; d < dsp[j].size(); ++d)
+        by_col[dsp[j][d]].push_back(((static_cast<unsigned>(p) * rec + 3 + static_cast<unsigned>(d)) << 8) | c);
+    }
+    const int row = 1 + s, pi = (row - 1) / part;
+    for (int k = 0; k < ns; ++k)
+      if (!by_col[k].empty()) parts[pi].push_back(Slot{row - (1 + pi * part), 1 + k, by_col[k]});
+  }
+  size_t spn = 1;
+  for (auto& v : sp_ops) spn = std::max(spn, v.size());
+  std::vector<unsigned> sp_flat(spn * kThreads, static_cast<unsigned>(nr) << 8);
+  for (int t = 0; t < kThreads; ++t)
+    for (size_t j = 0; j < sp_ops[t].size(); ++j) sp_flat[j * kThreads + t] = sp_ops[t][j];
+  // slots
+  std::vector<std::vector<std::vector<unsigned long long>>> th_ops(nparts, std::vector<std::vector<unsigned long long>>(kThreads));
+  size_t csn = 1;
+  for (int pi = 0; pi < nparts; ++pi) {
+    std::vector<Slot>& sl = parts[pi];
+    std::vector<int> order(sl.size());
+    for (size_t i = 0; i < sl.size(); ++i) order[i] = static_cast<int>(i);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return sl[a].terms.size() > sl[b].terms.size(); });
+    std::vector<size_t> load(kThreads, 0);
+    std::vector<std::vector<int>> own(kThreads);
+    for (int i : order) {
+      const int th = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+      load[th] += sl[i].terms.size();
+      own[th].push_back(i);
+    }
+    for (int th = 0; th < kThreads; ++th) {
+      std::sort(own[th].begin(), own[th].end());
+      for (int i : own[th]) {
+        const unsigned long long dst = (static_cast<unsigned long long>(sl[i].row) << 16) | static_cast<unsigned>(sl[i].col);
+        for (size_t e = 0; e < sl[i].terms.size(); ++e) {
+          const unsigned long long hi = e + 1 == sl[i].terms.size() ? dst : 0xffffffffull;
+          th_ops[pi][th].push_back((hi << 32) | sl[i].terms[e]);
+        }
+      }
+      csn = std::max(csn, th_ops[pi][th].size());
+    }
+  }
+  const unsigned long long pad = (0xffffffffull << 32) | (static_cast<unsigned long long>(zero_rec) << 8);
+  std::vector<unsigned long long> cs_flat(static_cast<size_t>(nparts) * csn * kThreads, pad);
+  for (int pi = 0; pi < nparts; ++pi)
+    for (int th = 0; th < kThreads; ++th)
+      for (size_t j = 0; j < th_ops[pi][th].size(); ++j)
+        cs_flat[(static_cast<size_t>(pi) * csn + j) * kThreads + th] = th_ops[pi][th][j];
+  os << "#define BK_SPN " << spn << "\n#define BK_CS_PARTS " << nparts << "\n#define BK_CSN " << csn << "\n";
+  emit_array(os, "unsigned", "bk_sp_ops", sp_flat);
+  os << "static __device__ const unsigned long long bk_cs_ops[" << cs_flat.size() << "] = {";
+  for (size_t i = 0; i < cs_flat.size(); ++i) os << (i ? ", " : "") << cs_flat[i] << "ull";
+  os << "};\n";
 }
 
 std::string generate_source(const Mechanism& m, int dense_limit) {
@@ -644,7 +757,9 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
   }
   if (wave) {
     const int md = emit_wave_tables(os, m);
-    os << "#define BK_PART " << block_part_rows(n, nr > 0 ? nr : 1, md) << "\n";
+    const int part = block_part_rows(n, nr > 0 ? nr : 1, md);
+    os << "#define BK_PART " << part << "\n";
+    emit_block_jac_tables(os, m, part, md);
     os << kKernels;
     os << kWave;
     os << kBlock;

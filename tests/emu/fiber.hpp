@@ -140,6 +140,40 @@ inline d4 mfma_f64_16x16x4(double a, double bv, d4 c, int line) {
   return d;
 }
 
+// DPP move (v_mov_b32_dpp) for the controls the device code uses: quad_perm (0x00-0xff), row_mirror
+// (0x140), row_half_mirror (0x141), row_bcast:15 (0x142) and row_bcast:31 (0x143).  A lane whose
+// row is off in row_mask, or whose source lane does not exist, gets `old` (bound_ctrl off; every
+// bank is enabled in the device code).
+inline int dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl, int line) {
+  Block& B = *g_blk;
+  long long k;
+  const int b = wave_arrive(line, k);
+  B.slot[b][B.cur] = static_cast<uint32_t>(src);
+  yield_next();
+  wave_check(k, b, line);
+  if (bank_mask != 0xf || bound_ctrl) { std::fprintf(stderr, "dpp: unsupported bank_mask/bound_ctrl\n"); std::_Exit(8); }
+  const int w0 = B.cur & ~63, l = B.cur & 63, row = l >> 4, lr = l & 15;
+  if (!((row_mask >> row) & 1)) return old;
+  int s;
+  if (ctrl <= 0xff) {
+    s = (l & ~3) | ((ctrl >> (2 * (l & 3))) & 3);
+  } else if (ctrl == 0x140) {
+    s = (l & ~15) | (15 - lr);
+  } else if (ctrl == 0x141) {
+    s = (l & ~7) | (7 - (l & 7));
+  } else if (ctrl == 0x142) {
+    if (row == 0) return old;
+    s = 16 * (row - 1) + 15;
+  } else if (ctrl == 0x143) {
+    if (row < 2) return old;
+    s = 31;
+  } else {
+    std::fprintf(stderr, "dpp: unsupported control %#x\n", ctrl);
+    std::_Exit(8);
+  }
+  return static_cast<int>(static_cast<uint32_t>(B.slot[b][w0 + s]));
+}
+
 // workgroup barrier: every thread must reach it at the same line
 inline void barrier(int line) {
   Block& B = *g_blk;
@@ -230,6 +264,7 @@ inline int __lane_id() { return emu::g_blk->cur & 63; }
 #define __builtin_amdgcn_readlane(v, src) emu::exchange<int>((v), (src), __LINE__)
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) emu::mfma_f64_16x16x4((a), (b), (c), __LINE__)
 #define __ballot(p) emu::ballot((p), __LINE__)
+#define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) emu::dpp((old), (src), (ctrl), (rm), (bm), (bc), __LINE__)
 #define __builtin_amdgcn_wave_barrier() ((void)emu::exchange<int>(0, 0, __LINE__))
 #define __builtin_amdgcn_fence(order, scope) ((void)0)
 inline int __ffsll(long long v) { return __builtin_ffsll(v); }
