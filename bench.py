@@ -46,7 +46,9 @@ def main():
     ap.add_argument("--skip-adjoint", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-kernels", action="store_true")
-    ap.add_argument("--skip-large", action="store_true", help="skip the 53-species mechanism legs")
+    ap.add_argument("--skip-large", action="store_true", help="skip the 53- and 150-species mechanism legs")
+    ap.add_argument("--c2-cells", type=int, default=4096,
+                    help="cells of the 53-species Rosenbrock state set integrated over 1e-5 s (262144 = all)")
     ap.add_argument("--probe", type=int, default=None,
                     help="probe_attempts of the persistent form (default: the library's)")
     ap.add_argument("--cpu-cells", type=int, default=128, help="oracle cells per host process")
@@ -162,8 +164,15 @@ def main():
                                        STATE_CONFIGS)
 
     if not args.skip_adjoint:
-        extras["adjoint"] = adjoint_ratio(gm, torch, np, dev, Tape, default_options, CHEM_BE, sample_states,
-                                          loss_weights, STATE_CONFIGS)
+        # the differentiation workload: 53-species mechanism, 16,384 cells, 500 x 2e-8 s, checkpoints every 50
+        gm53 = Mechanism(mechanism_file("ch4like_53_325"), KERNEL_CACHE)
+        c3 = STATE_CONFIGS["adjoint_methane"]
+        extras["adjoint"] = adjoint_ratio(gm53, torch, np, dev, Tape, default_options, CHEM_BE, sample_states,
+                                          loss_weights, STATE_CONFIGS, mech_name="ch4like_53_325",
+                                          T_range=c3.T_range, alpha=c3.alpha, reps=1)
+        del gm53
+        extras["adjoint_h2like_10_27"] = adjoint_ratio(gm, torch, np, dev, Tape, default_options, CHEM_BE,
+                                                       sample_states, loss_weights, STATE_CONFIGS)
 
         extras["adjoint_rosenbrock"] = ros2_adjoint_ratio(gm, torch, np, dev, Tape, default_options, sample_states,
                                                           loss_weights, cfg)
@@ -399,9 +408,10 @@ def be_small_rate(gm, torch, np, dev, default_options, CHEM_BE, sample_states, S
 
 
 def adjoint_ratio(gm, torch, np, dev, Tape, default_options, CHEM_BE, sample_states, loss_weights, STATE_CONFIGS,
-                  mech_name="h2like_10_27", T_range=(1000.0, 1500.0), alpha=1.0):
+                  mech_name="h2like_10_27", T_range=(1000.0, 1500.0), alpha=1.0, reps=2):
     """Backward-Euler forward (with tape) vs discrete adjoint on the adjoint workload's 16,384
-    cells: 500 x 2e-8 s steps, checkpoints every 50, loss weights w ~ N(0, 1)."""
+    cells (seed 2003): 500 x 2e-8 s steps, checkpoints every 50, dL/dy_N = w ~ N(0, 1).  Each time
+    is the best of `reps` runs after one untimed forward + adjoint."""
     cfg = STATE_CONFIGS["adjoint_methane"]
     n = cfg.n_cells
     T, p, Y = sample_states(gm.ns, n, cfg.seed, T_range, alpha, cfg.p)
@@ -428,13 +438,14 @@ def adjoint_ratio(gm, torch, np, dev, Tape, default_options, CHEM_BE, sample_sta
         y.copy_(y0)
         gm.chem_integrate(n, n, y, None, opts, tp, st, cnt)
 
+    log(f"adjoint ({mech_name}): untimed forward + adjoint")
     fwd(tape)
     gm.chem_integrate_adjoint(tape, None, lam, d0, g)
-    t_fwd = min(timed(lambda: fwd(None)) for _ in range(2))
-    t_fwd_tape = min(timed(lambda: fwd(tape)) for _ in range(2))
-    t_adj = min(timed(lambda: gm.chem_integrate_adjoint(tape, None, lam, d0, g)) for _ in range(2))
-    r = {"workload": f"{mech_name}, {n} cells, T0~U[{T_range[0]:.0f},{T_range[1]:.0f}] K, backward Euler "
-                     "500 x 2e-8 s, checkpoints every 50",
+    t_fwd = min(timed(lambda: fwd(None)) for _ in range(reps))
+    t_fwd_tape = min(timed(lambda: fwd(tape)) for _ in range(reps))
+    t_adj = min(timed(lambda: gm.chem_integrate_adjoint(tape, None, lam, d0, g)) for _ in range(reps))
+    r = {"workload": f"{mech_name}, {n} cells, T0~U[{T_range[0]:.0f},{T_range[1]:.0f}] K, Dirichlet({alpha:g}), "
+                     "backward Euler 500 x 2e-8 s, checkpoints every 50",
          "forward_ms": t_fwd * 1e3, "forward_with_tape_ms": t_fwd_tape * 1e3, "adjoint_ms": t_adj * 1e3,
          "adjoint_over_forward": t_adj / t_fwd, "total_over_forward": (t_fwd_tape + t_adj) / t_fwd,
          "newton_iterations": int(cnt[2].sum().item()), "failed_cells": int((st != 0).sum().item())}
@@ -491,13 +502,17 @@ def ros2_adjoint_ratio(gm, torch, np, dev, Tape, default_options, sample_states,
 
 
 def large_mechanism_legs(torch, np, dev, args):
-    """The 53-species / 325-reaction mechanism: source-term (one cell per lane) and Jacobian (one
-    wavefront per cell) kernels over the 262,144-cell state set.  Its integration is switched off
-    in this version (reported as such)."""
-    from paper_2510_10005_amd import Mechanism
+    """The 53-species / 325-reaction mechanism: its API kernels over the 262,144-cell state set and
+    the adaptive Rosenbrock integration of args.c2_cells cells of that distribution over 1e-5 s
+    (block form, persistent work queue with the probe/resume schedule, autotuned grid), with parity
+    on the oracle's stored samples when the cell count is the samples' (4,096); the 150-species
+    mechanism's API kernels."""
+    import json as _json
+
+    from paper_2510_10005_amd import CHEM_PERSISTENT, CHEM_ROS2, Mechanism, default_options
     from paper_2510_10005_amd.flops import MechanismCounts
     from synth import mechanism_file
-    from synth.states import STATE_CONFIGS, sample_states
+    from synth.states import STATE_CONFIGS, sample_config, sample_states
     path = mechanism_file("ch4like_53_325")
     gm = Mechanism(path, KERNEL_CACHE)
     counts = MechanismCounts(path)
@@ -507,10 +522,89 @@ def large_mechanism_legs(torch, np, dev, args):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     y0 = torch.empty((gm.n, n), dtype=torch.float64, device=dev)
     gm.chem_state_from_TPY(n, n, t(T), t(p), t(Y.T), y0)
-    out = {"workload": f"ch4like_53_325, {n} cells, T0~U[800,2600] K, Dirichlet(0.5); source terms one cell per "
-                       "lane, Jacobian one wavefront per cell",
-           "integration": "switched off in this version (GPU run did not complete; cause not identified)"}
+    out = {"workload": f"ch4like_53_325, {n} cells (seed {cfg.seed}), T0~U[800,2600] K, Dirichlet(0.5); source "
+                       "terms one cell per lane, Jacobian one wavefront per cell"}
     out["api_kernels"] = api_kernel_rates(gm, counts, y0, n, torch, dev, reps=3)
+    # adaptive Rosenbrock over the split step on nc cells of the set's distribution and seed (for
+    # nc < 262,144 these are sample_config's nc cells, not a prefix of the full set)
+    nc = max(1, min(args.c2_cells, n))
+    if nc == n:
+        y = y0.clone()
+    else:
+        Tc, pc, Yc = sample_config("ros2_methane", gm.ns, nc)
+        y = torch.empty((gm.n, nc), dtype=torch.float64, device=dev)
+        gm.chem_state_from_TPY(nc, nc, t(Tc), t(pc), t(Yc.T), y)
+    yi = y.clone()
+    st = torch.empty(nc, dtype=torch.int32, device=dev)
+    cnt = torch.zeros((3, nc), dtype=torch.int32, device=dev)
+    opts = default_options(method=CHEM_ROS2, dt=1e-5, n_steps=0, rtol=1e-6, atol=1e-10, form=CHEM_PERSISTENT)
+    nt = min(nc, 1024)
+    log(f"53-species Rosenbrock: autotuning on {nt} cells")
+    gm.chem_autotune(nt, nc, yi, None, opts)
+    block, grid = gm.chem_get_launch(CHEM_ROS2, CHEM_PERSISTENT)
+    log(f"53-species Rosenbrock: {nc} cells over 1e-5 s, launch {block} x {grid}")
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    gm.chem_integrate(nc, nc, y, None, opts, None, st, cnt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - a
+    acc = cnt[0].to(torch.float64)
+    n_acc, n_rej = int(cnt[0].sum().item()), int(cnt[1].sum().item())
+    att = counts.ros2_attempt()
+    ros2 = {"workload": f"{nc} cells with the 262,144-cell set's distribution and seed, adaptive 2-stage Rosenbrock (rtol 1e-6, "
+                        "atol 1e-10) over one 1e-5 s split step, block form (one cell per 256-thread workgroup), "
+                        "persistent work queue, probe/resume schedule, autotuned grid",
+            "cells": nc, "launch": {"block": block, "grid": grid}, "ms": wall * 1e3,
+            "accepted_substeps": n_acc, "rejected_attempts": n_rej,
+            "cell_substeps_per_s": n_acc / wall, "attempts_per_s": (n_acc + n_rej) / wall,
+            "substeps_min": int(acc.min().item()), "substeps_median": float(acc.median().item()),
+            "substeps_max": int(acc.max().item()),
+            "substep_max_over_min": float(acc.max().item() / max(1.0, acc.min().item())),
+            "flops_per_attempt": att.flops,
+            "tflops_algorithmic": att.flops * (n_acc + n_rej) / wall / 1e12,
+            "failed_cells": int((st != 0).sum().item())}
+    log(f"53-species Rosenbrock: {wall:.2f} s, {n_acc} accepted + {n_rej} rejected, {n_acc / wall:.3e} "
+        f"cell-substeps/s, substeps per cell {ros2['substeps_min']}..{ros2['substeps_max']}")
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "ros2_methane_samples.json")
+    if os.path.exists(gold):
+        import oracle
+        ref = _json.load(open(gold))
+        om = oracle.load_mechanism(path)
+        rows = [r for r in ref["cells"] if r["cell"] < nc] if nc == ref["subset"] else []
+        if rows:
+            idx = [r["cell"] for r in rows]
+            yg = y[:, idx].cpu().numpy().T
+            cg = cnt[:, idx].cpu().numpy()
+            yo = np.array([r["y"] for r in rows])
+            same = (cg[0] == np.array([r["accepted"] for r in rows])) & \
+                   (cg[1] == np.array([r["rejected"] for r in rows]))
+            # T relative; species as mass fractions relative to max(|Y_ref|, 1e-12)
+            rho = (yo[:, 1:] * om.W).sum(axis=1)
+            eT = np.abs(yg[:, 0] - yo[:, 0]) / np.abs(yo[:, 0])
+            Yg, Yo = yg[:, 1:] * om.W / rho[:, None], yo[:, 1:] * om.W / rho[:, None]
+            err = np.maximum(eT, (np.abs(Yg - Yo) / np.maximum(np.abs(Yo), 1e-12)).max(axis=1))
+            ros2["parity"] = {"cells": len(idx), "cells_same_step_counts": int(same.sum()),
+                              "max_rel_err": float(err.max()), "bar": 1e-8,
+                              "reference": "oracle, stored per cell (tests/golden/ros2_methane_samples.json)"}
+            log(f"53-species Rosenbrock parity: {int(same.sum())} of {len(idx)} sampled cells with equal step "
+                f"counts, max rel err {err.max():.2e}")
+    out["rosenbrock"] = ros2
+    del y, yi, y0
+    # 150-species mechanism: API kernels on the first 16,384 cells of its state set
+    path150 = mechanism_file("large_150_1000")
+    g150 = Mechanism(path150, KERNEL_CACHE)
+    c150 = MechanismCounts(path150)
+    cfg4 = STATE_CONFIGS["ros2_large"]
+    n4 = 16384
+    T4, p4, Y4 = sample_states(g150.ns, n4, cfg4.seed, cfg4.T_range, cfg4.alpha, cfg4.p)
+    y4 = torch.empty((g150.n, n4), dtype=torch.float64, device=dev)
+    g150.chem_state_from_TPY(n4, n4, t(T4), t(p4), t(Y4.T), y4)
+    out["large_150_1000"] = {
+        "workload": f"large_150_1000 (n = 151), first {n4} cells of its 65,536-cell set; source terms and "
+                    "Jacobian in the block form (one cell per 256-thread workgroup)",
+        "api_kernels": api_kernel_rates(g150, c150, y4, n4, torch, dev, reps=2),
+        "integration": "not run: the integrators of this mechanism (factors in device memory) are off on the GPU "
+                       "after an illegal memory access whose cause has not been shown"}
     return out
 
 

@@ -54,7 +54,10 @@ def sample_states(n_species: int, n_cells: int, seed: int, T_range=(1000.0, 1500
 
 
 def sample_config(name: str, n_species: int, n_cells: int | None = None):
-    """States of one named workload (optionally only its first ``n_cells`` cells)."""
+    """States of one named workload, or ``n_cells`` states with its distribution and seed.
+
+    All temperatures are drawn before the compositions, so a smaller set is not the first cells of
+    the full one (take a prefix of the full set for that)."""
     c = STATE_CONFIGS[name]
     n = c.n_cells if n_cells is None else n_cells
     return sample_states(n_species, n, c.seed, c.T_range, c.alpha, c.p)

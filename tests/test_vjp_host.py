@@ -8,6 +8,8 @@ compiled for the host (tests/emu/vjp_driver.cpp) and mech_vjp is evaluated on se
 * with dual numbers y + eps d: the value parts again, and the dual parts against complex-step
   directional derivatives of the oracle's Jacobian and dS/dlnA along d ((J'(y)[d])^T u and
   u^T (dS/dlnA)'(y)[d]), which the adjoint's second-derivative terms use.
+Each case is built twice: g++ -O1, and clang -O3 with ASan, UBSan and automatic variables filled
+with a pattern (so an uninitialised read would show as a wrong or non-finite value).
 """
 
 import os
@@ -40,21 +42,47 @@ def generator(tmp_path_factory):
     return cxx, gen
 
 
-def _build(generator, tmp_path, name):
+def _clang():
+    for c in ("/opt/rocm/llvm/bin/clang++", shutil.which("clang++")):
+        if c and os.path.exists(c):
+            return c
+    return None
+
+
+# build variants: g++ -O1; clang -O3 with AddressSanitizer, UndefinedBehaviorSanitizer and every
+# automatic variable pre-filled with a pattern (an uninitialised read then shows up as a wrong or
+# non-finite value instead of a benign leftover)
+BUILDS = {
+    "gcc-O1": None,
+    "clang-O3-asan-ubsan-pattern": ["-O3", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                                    "-ftrivial-auto-var-init=pattern"],
+}
+
+
+def _build(generator, tmp_path, name, build="gcc-O1"):
     cxx, gen = generator
     path = mechanism_file(name)
     src = subprocess.run([gen, path], capture_output=True, text=True, check=True).stdout
     (tmp_path / "mech_block.hip").write_text(src[:src.index(MARK)])
     exe = str(tmp_path / "vjpd")
-    subprocess.run([cxx, "-O1", "-std=c++17", "-Wno-unknown-pragmas", "-include", "cstdlib", "-I", str(tmp_path),
-                    os.path.join(EMU, "vjp_driver.cpp"), "-o", exe], check=True)
+    flags = BUILDS[build]
+    if flags is None:
+        cmd = [cxx, "-O1"]
+    else:
+        cl = _clang()
+        if cl is None:
+            pytest.skip("no clang++")
+        cmd = [cl] + flags
+    subprocess.run(cmd + ["-std=c++17", "-Wno-unknown-pragmas", "-include", "cstdlib", "-I", str(tmp_path),
+                          os.path.join(EMU, "vjp_driver.cpp"), "-o", exe], check=True)
     return exe, oracle.load_mechanism(path)
 
 
+@pytest.mark.parametrize("build", list(BUILDS))
 @pytest.mark.parametrize("name", ["tiny_8_14", "h2like_10_27", "sri_12_30", "plog_12_30"])
 @pytest.mark.parametrize("energy", [0, 1])
-def test_vjp_matches_oracle(generator, tmp_path, name, energy):
-    exe, m = _build(generator, tmp_path, name)
+def test_vjp_matches_oracle(generator, tmp_path, name, energy, build):
+    exe, m = _build(generator, tmp_path, name, build)
     nc = 6
     T, p, Y = sample_config("ros2_1m", m.ns, nc)
     y = oracle.state_from_TPY(m, T, p, Y)
