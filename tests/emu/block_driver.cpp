@@ -13,6 +13,7 @@
 //     the factors [NY][NY], the pivot row of each step [NY] and the reciprocal pivots [NY]
 #include "fiber.hpp"
 #include <vector>
+#define BK_OCC   // no GPU occupancy attribute in the host build
 #include "src.hip"
 
 static bool read_all(const char* path, std::vector<double>& v) {
