@@ -580,7 +580,8 @@ def large_mechanism_legs(torch, np, dev, args):
     log(f"53-species Rosenbrock: autotuning on {nt} cells")
     gm.chem_autotune(nt, nc, yi, None, opts)
     block, grid = gm.chem_get_launch(CHEM_ROS2, CHEM_PERSISTENT)
-    log(f"53-species Rosenbrock: {nc} cells over 1e-5 s, launch {block} x {grid}")
+    lus = gm.chem_get_lu_strategy(CHEM_ROS2)
+    log(f"53-species Rosenbrock: {nc} cells over 1e-5 s, launch {block} x {grid}, LU strategy {lus}")
     # more than 32,768 cells: consecutive launches of 32,768 cells each (one line per launch)
     chunk = nc if nc <= 32768 else 32768
     wall = 0.0
@@ -606,7 +607,8 @@ def large_mechanism_legs(torch, np, dev, args):
     ros2 = {"workload": f"{nc} cells with the 262,144-cell set's distribution and seed, adaptive 2-stage Rosenbrock (rtol 1e-6, "
                         "atol 1e-10) over one 1e-5 s split step, block form (one cell per 256-thread workgroup), "
                         "persistent work queue, probe/resume schedule, autotuned grid",
-            "cells": nc, "launch": {"block": block, "grid": grid, "cells_per_launch": chunk}, "ms": wall * 1e3,
+            "cells": nc, "launch": {"block": block, "grid": grid, "cells_per_launch": chunk, "lu_strategy": lus},
+            "ms": wall * 1e3,
             "accepted_substeps": n_acc, "rejected_attempts": n_rej,
             "cell_substeps_per_s": n_acc / wall, "attempts_per_s": (n_acc + n_rej) / wall,
             "substeps_min": int(acc.min().item()), "substeps_median": float(acc.median().item()),

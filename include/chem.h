@@ -316,11 +316,29 @@ chem_err chem_integrate_adjoint(const chem_mech* mech, chem_tape* tape, const do
  * Kernel launch configuration of chem_integrate for a method/form: threads per block and blocks
  * of the persistent grid (0 = library default).  chem_autotune times the candidates on the given
  * cells (which it leaves unchanged) and keeps the fastest; chem_get_launch reports the current one.
+ * For CHEM_BE and CHEM_ROS2 of mechanisms with 24 < n <= 64 (block form, factors in LDS) the
+ * candidates also span the LU strategy of the per-cell direct solve (Section 3.4).
  */
 chem_err chem_set_launch(chem_mech* mech, int method, int form, int block, int grid);
 chem_err chem_get_launch(const chem_mech* mech, int method, int form, int* block, int* grid);
 chem_err chem_autotune(chem_mech* mech, int64_t n_cells, int64_t ld, const double* y, const double* lnA,
                        const chem_integrator_opts* opts, void* stream);
+
+/*
+ * LU strategy of the persistent integration kernel of a method (the direct solve of Section 3.4,
+ * partial pivoting in both): 0 (default) = the panel of four columns factored in registers by
+ * one wavefront with a DPP wave maximum and one barrier per panel, triangular solves by one
+ * wavefront in registers; 1 = the panel factored in LDS with a 64-bit key maximum and the pivot
+ * rows staged in LDS (several barriers per panel), solves blocked by 16 steps.  Both update the
+ * trailing matrix with FP64 matrix-core products.  Strategy 1 exists for CHEM_BE and CHEM_ROS2 of
+ * mechanisms with 24 < n <= 64; elsewhere chem_set_lu_strategy(…, 1) returns CHEM_EUNSUPPORTED
+ * (and mechanisms with n > 64 always use the LDS-panel LU).  A run that records an adjoint tape
+ * uses strategy 0, as the adjoint's replays do.  Results of the two strategies agree to rounding.
+ * Errors: CHEM_EINVAL for a null mechanism/pointer, an unknown method or a strategy other than
+ * 0 or 1.
+ */
+chem_err chem_set_lu_strategy(chem_mech* mech, int method, int strategy);
+chem_err chem_get_lu_strategy(const chem_mech* mech, int method, int* strategy);
 
 #ifdef __cplusplus
 }

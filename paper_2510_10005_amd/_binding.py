@@ -31,6 +31,7 @@ EXPORTED = [
     "chem_mass_fractions", "chem_state_from_TPY_vjp", "chem_mass_fractions_vjp", "chem_integrate",
     "chem_tape_create", "chem_tape_create_ros2", "chem_tape_free", "chem_integrate_adjoint", "chem_set_launch",
     "chem_get_launch", "chem_autotune", "chem_T_from_energy", "chem_cfd_source", "chem_integrate_noalloc",
+    "chem_set_lu_strategy", "chem_get_lu_strategy",
 ]
 
 
@@ -106,6 +107,8 @@ def load():
     lib.chem_set_launch.argtypes = [_P, _I, _I, _I, _I]
     lib.chem_get_launch.argtypes = [_P, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]
     lib.chem_autotune.argtypes = [_P, _I64, _I64, _P, _P, ctypes.POINTER(IntegratorOptions), _P]
+    lib.chem_set_lu_strategy.argtypes = [_P, _I, _I]
+    lib.chem_get_lu_strategy.argtypes = [_P, _I, ctypes.POINTER(_I)]
     lib.chem_T_from_energy.argtypes = [_P, _I64, _I64, _P, _P, _P, _I, _I, _P, _P]
     lib.chem_cfd_source.argtypes = [_P, _I64, _I64, _P, _P, ctypes.c_double, _P, _P]
     for name in EXPORTED:
@@ -234,6 +237,14 @@ class Mechanism:
         _check(self.lib.chem_get_launch(self.handle, method, form, ctypes.byref(b), ctypes.byref(g)),
                "chem_get_launch")
         return b.value, g.value
+
+    def chem_set_lu_strategy(self, method, strategy):
+        _check(self.lib.chem_set_lu_strategy(self.handle, method, strategy), "chem_set_lu_strategy")
+
+    def chem_get_lu_strategy(self, method):
+        v = _I()
+        _check(self.lib.chem_get_lu_strategy(self.handle, method, ctypes.byref(v)), "chem_get_lu_strategy")
+        return v.value
 
     def chem_autotune(self, n, ld, y, lnA, opts):
         _check(self.lib.chem_autotune(self.handle, n, ld, _ptr(y), _ptr(lnA), ctypes.byref(opts), _stream()),

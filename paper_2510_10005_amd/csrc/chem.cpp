@@ -53,13 +53,17 @@ const char* kKernelNames[] = {
     "chem_k_be_init",       "chem_k_be_step",          "chem_k_be_adjoint",       "chem_k_reduce_blocks",
     "chem_k_sched_scan",    "chem_k_sched_scatter",    "chem_k_jac_transpose",    "chem_k_ros2_persistent_rec",
     "chem_k_ros2_adjoint",  "chem_k_sdirk2_persistent", "chem_k_sdirk4_persistent",
-    "chem_k_yass_persistent", "chem_k_T_from_energy", "chem_k_cfd_source"};
+    "chem_k_yass_persistent", "chem_k_T_from_energy", "chem_k_cfd_source", "chem_k_ros2_persistent_lup",
+    "chem_k_be_persistent_lup"};
 enum KernelId {
   K_THERMO, K_SOURCE, K_JACOBIAN, K_TPY, K_MASSFRAC, K_TPY_VJP, K_MASSFRAC_VJP, K_FILL_U64,
   K_ROS2_PERSISTENT, K_ROS2_INIT, K_ROS2_STEP, K_BE_PERSISTENT, K_BE_INIT, K_BE_STEP, K_BE_ADJOINT,
   K_REDUCE_BLOCKS, K_SCHED_SCAN, K_SCHED_SCATTER, K_JAC_TRANSPOSE, K_ROS2_PERSISTENT_REC, K_ROS2_ADJOINT,
-  K_SDIRK2_PERSISTENT, K_SDIRK4_PERSISTENT, K_YASS_PERSISTENT, K_T_FROM_ENERGY, K_CFD_SOURCE, K_COUNT
+  K_SDIRK2_PERSISTENT, K_SDIRK4_PERSISTENT, K_YASS_PERSISTENT, K_T_FROM_ENERGY, K_CFD_SOURCE,
+  K_ROS2_PERSISTENT_LUP, K_BE_PERSISTENT_LUP, K_COUNT
 };
+// kernels of LU strategy 1 (block form with the factors in LDS only)
+bool lu_strategy_kernel(int k) { return k == K_ROS2_PERSISTENT_LUP || k == K_BE_PERSISTENT_LUP; }
 // kernels that only the register-resident form (n <= kDenseLimit) has
 bool dense_only(int k) {
   return k == K_ROS2_PERSISTENT_REC || k == K_ROS2_ADJOINT || k == K_SDIRK2_PERSISTENT || k == K_SDIRK4_PERSISTENT ||
@@ -143,7 +147,7 @@ std::vector<std::string> compile_options(const std::string& arch) {
 // a larger one is split into one program per group, compiled concurrently, because its code is
 // large enough that a single compile is slow.
 constexpr int kGroups = 4;
-const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1, 0, 1, 3, 2, 2, 2, 0, 0};
+const int kKernelGroup[K_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 0, 1, 1, 0, 1, 3, 2, 2, 2, 0, 0, 1, 2};
 
 struct CodeObject {
   std::string code, path;
@@ -283,6 +287,7 @@ struct chem_mech {
   DevBuf lnA_default, queue, ws, wst, counters_internal, running, seg, gws, gpart, sched, order, jstage;
   unsigned int* running_host = nullptr;
   int launch_block[5][2] = {};  // [method][form]
+  int lu_strategy[5] = {};      // [method]: 0 default, 1 LDS-panel LU (block form, factors in LDS)
   int launch_grid[5][2] = {};
   size_t max_shmem = 0;         // LDS bytes one block may use on this device
   // The workspaces above are shared by every stream: each call that uses them records `fence` on
@@ -434,6 +439,17 @@ int occupancy_blocks(const chem_mech* M, KernelId k, int block) {
   return nb;
 }
 
+// the persistent kernel of a method under the mechanism's LU strategy (strategy 1 only where its
+// kernel exists: block form with the factors in LDS; a run that records a tape uses strategy 0,
+// the one the adjoint's replays use)
+KernelId persistent_kernel_of(const chem_mech* M, int method, bool tape = false) {
+  const KernelId k = persistent_kernel(method);
+  if (tape || M->lu_strategy[method] != 1) return k;
+  if (method == CHEM_ROS2 && M->fn[K_ROS2_PERSISTENT_LUP]) return K_ROS2_PERSISTENT_LUP;
+  if (method == CHEM_BE && M->fn[K_BE_PERSISTENT_LUP]) return K_BE_PERSISTENT_LUP;
+  return k;
+}
+
 void persistent_config(const chem_mech* M, int method, KernelId k, int& block, unsigned& grid) {
   block = M->launch_block[method][CHEM_PERSISTENT] ? M->launch_block[method][CHEM_PERSISTENT] : 64;
   if (M->wave) block = kBlockThreads;
@@ -537,9 +553,10 @@ chem_err chem_load_mechanism(const char* path, const char* cache_dir, chem_mech*
     if (M->wave && dense_only(k)) continue;
     hipModule_t md = M->modules[M->modules.size() == 1 ? 0 : kKernelGroup[k]];
     const hipError_t ge = hipModuleGetFunction(&M->fn[k], md, kKernelNames[k]);
-    // the block form has no plain-form step kernels and no adjoint kernel: those stay null and the
-    // entry points that need them refuse the request
-    if (ge != hipSuccess && !(M->wave && (k == K_ROS2_STEP || k == K_BE_STEP || k == K_BE_ADJOINT))) {
+    // the block form has no plain-form step kernels (and mechanisms without LDS-resident factors no
+    // second LU strategy): those stay null and the entry points that need them refuse the request
+    if (ge != hipSuccess && !lu_strategy_kernel(k) &&
+        !(M->wave && (k == K_ROS2_STEP || k == K_BE_STEP || k == K_BE_ADJOINT))) {
       HIP_TRY(ge);
     }
     if (ge != hipSuccess) {
@@ -877,7 +894,7 @@ chem_err integrate_impl(chem_mech* M, int64_t n, int64_t ld, double* y, const do
   }
   const int method = opts->method;
   if (opts->form == CHEM_PERSISTENT) {
-    const KernelId k = (method == CHEM_ROS2 && hs) ? K_ROS2_PERSISTENT_REC : persistent_kernel(method);
+    const KernelId k = (method == CHEM_ROS2 && hs) ? K_ROS2_PERSISTENT_REC : persistent_kernel_of(M, method, tape);
     int block;
     unsigned grid;
     persistent_config(M, method, k, block, grid);
@@ -1116,13 +1133,34 @@ chem_err chem_get_launch(const chem_mech* M, int method, int form, int* block, i
   if (form == CHEM_PERSISTENT) {
     int b;
     unsigned g;
-    persistent_config(M, method, persistent_kernel(method), b, g);
+    persistent_config(M, method, persistent_kernel_of(M, method), b, g);
     *block = b;
     *grid = static_cast<int>(g);
   } else {
     *block = M->wave ? kBlockThreads : (M->launch_block[method][form] ? M->launch_block[method][form] : 64);
     *grid = 0;
   }
+  return CHEM_OK;
+}
+
+chem_err chem_set_lu_strategy(chem_mech* M, int method, int strategy) {
+  if (!M) return fail(CHEM_EINVAL, "null mechanism");
+  if (!known_method(method)) return fail(CHEM_EINVAL, "unknown method");
+  if (strategy != 0 && strategy != 1) return fail(CHEM_EINVAL, "LU strategy must be 0 or 1");
+  if (strategy == 1) {
+    const KernelId k = method == CHEM_ROS2 ? K_ROS2_PERSISTENT_LUP : (method == CHEM_BE ? K_BE_PERSISTENT_LUP : K_COUNT);
+    if (k == K_COUNT || !M->fn[k])
+      return fail(CHEM_EUNSUPPORTED, "LU strategy 1 exists for backward Euler and Rosenbrock of mechanisms with "
+                                     "24 < n <= 64 (block form, factors in LDS)");
+  }
+  M->lu_strategy[method] = strategy;
+  return CHEM_OK;
+}
+
+chem_err chem_get_lu_strategy(const chem_mech* M, int method, int* strategy) {
+  if (!M || !strategy) return fail(CHEM_EINVAL, "null argument");
+  if (!known_method(method)) return fail(CHEM_EINVAL, "unknown method");
+  *strategy = M->lu_strategy[method];
   return CHEM_OK;
 }
 
@@ -1144,11 +1182,15 @@ chem_err chem_autotune(chem_mech* M, int64_t n, int64_t ld, const double* y, con
   hipEvent_t a, b;
   HIP_TRY(hipEventCreate(&a));
   HIP_TRY(hipEventCreate(&b));
-  const KernelId k = persistent_kernel(opts->method);
   float best = 1e30f;
-  int best_block = 64, best_grid = 0;
+  int best_block = 64, best_grid = 0, best_lus = 0;
   const int method = opts->method;
   const int prev_block = M->launch_block[method][CHEM_PERSISTENT], prev_grid = M->launch_grid[method][CHEM_PERSISTENT];
+  const int prev_lus = M->lu_strategy[method];
+  // LU strategies to try: 1 only where its kernels exist
+  std::vector<int> strategies = {0};
+  if ((method == CHEM_ROS2 && M->fn[K_ROS2_PERSISTENT_LUP]) || (method == CHEM_BE && M->fn[K_BE_PERSISTENT_LUP]))
+    strategies.push_back(1);
   // one timed trial of a launch shape on a copy of the cells
   auto trial = [&](int block, int grid, float& ms) -> chem_err {
     if (chem_err err = chem_set_launch(M, method, CHEM_PERSISTENT, block, grid)) return err;
@@ -1162,19 +1204,25 @@ chem_err chem_autotune(chem_mech* M, int64_t n, int64_t ld, const double* y, con
     return CHEM_OK;
   };
   e = CHEM_OK;
-  for (int block : {64, 128, 256}) {
-    if (M->wave && block != kBlockThreads) continue;  // one cell per 256-thread workgroup
-    if (!shmem_fits(M, k, block)) continue;  // the Rosenbrock kernels' LDS grows with the block
-    const int occ = occupancy_blocks(M, k, block);
-    for (int mult : {1, 2}) {
-      const int grid = occ * M->num_cu * mult;
-      float ms = 0.f;
-      if ((e = trial(block, grid, ms))) break;
-      if (ms < best) {
-        best = ms;
-        best_block = block;
-        best_grid = grid;
+  for (int lus : strategies) {
+    M->lu_strategy[method] = lus;
+    const KernelId k = persistent_kernel_of(M, method);
+    for (int block : {64, 128, 256}) {
+      if (M->wave && block != kBlockThreads) continue;  // one cell per 256-thread workgroup
+      if (!shmem_fits(M, k, block)) continue;  // the Rosenbrock kernels' LDS grows with the block
+      const int occ = occupancy_blocks(M, k, block);
+      for (int mult : {1, 2}) {
+        const int grid = occ * M->num_cu * mult;
+        float ms = 0.f;
+        if ((e = trial(block, grid, ms))) break;
+        if (ms < best) {
+          best = ms;
+          best_block = block;
+          best_grid = grid;
+          best_lus = lus;
+        }
       }
+      if (e) break;
     }
     if (e) break;
   }
@@ -1184,8 +1232,10 @@ chem_err chem_autotune(chem_mech* M, int64_t n, int64_t ld, const double* y, con
     // a failed trial leaves the configuration the mechanism had before
     M->launch_block[method][CHEM_PERSISTENT] = prev_block;
     M->launch_grid[method][CHEM_PERSISTENT] = prev_grid;
+    M->lu_strategy[method] = prev_lus;
     return e;
   }
+  M->lu_strategy[method] = best_lus;
   return chem_set_launch(M, method, CHEM_PERSISTENT, best_block, best_grid);
 }
 

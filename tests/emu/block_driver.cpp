@@ -1,14 +1,15 @@
 // Runs kernels of the generated block-form source (one cell per 256-thread workgroup) on the fiber
 // emulation (fiber.hpp).
 // Usage:
-//   block_driver be|ros2|ros2p n ld dt n_steps in.bin out.bin [grid]   (ros2p: probe/resume schedule)
+//   block_driver be|ros2|ros2p n ld dt n_steps in.bin out.bin [grid] [lu_strategy]
+//     (ros2p: probe/resume schedule; lu_strategy 1: the LDS-panel kernels, be and ros2 only)
 //     in.bin: state [NY][ld] then ln A [NR]; out.bin: state, status [ld], counters [3][ld]
 //   block_driver adj n ld dt n_steps K in.bin out.bin [grid]   (backward Euler with a tape, then its adjoint)
 //     in.bin: state [NY][ld], ln A [NR], dL/dy_N [NY][ld]; out.bin: state, status [ld], dL/dy0 [NY][ld],
 //     dL/dlnA [NR] (workgroup partials summed in workgroup order)
 //   block_driver src|jac n ld in.bin out.bin          (API kernels of mechanisms with n > 64)
 //     in.bin: state [NY][ld] then ln A [NR]; out.bin: sources [NY][ld] then (jac) [n][NY][NY]
-//   block_driver lu in.bin out.bin
+//   block_driver lu in.bin out.bin [lu_strategy]
 //     in.bin: A [NY][NY] row-major, b [NY], lam [NY]; out.bin: x = A^-1 b [NY], mu = A^-T lam [NY], then
 //     the factors [NY][NY], the pivot row of each step [NY] and the reciprocal pivots [NY]
 #include "fiber.hpp"
@@ -24,7 +25,8 @@ static bool read_all(const char* path, std::vector<double>& v) {
   return ok;
 }
 
-// standalone factor + solves: G = 0 I - (-A) = A
+// standalone factor + solves with LU strategy LUS: G = 0 I - (-A) = A
+template <int LUS>
 static void lu_kernel(const double* A, const double* b, const double* lam, double* x, double* mu, double* ws,
                       double* dump) {
   BkShared& sh = bk_shared();
@@ -36,9 +38,9 @@ static void lu_kernel(const double* A, const double* b, const double* lam, doubl
     sh.v2[t] = t < NY ? lam[t] : 0.0;
   }
   __syncthreads();
-  bk_lu(sh, F, 0.0);
-  bk_solve(sh, F, sh.v0, sh.v1);
-  bk_solve_T(sh, F, sh.v2, sh.v3);
+  bk_factor<LUS>(sh, F, 0.0);
+  bk_fsolve<LUS>(sh, F, sh.v0, sh.v1);
+  bk_fsolve_T<LUS>(sh, F, sh.v2, sh.v3);
   if (t < NY) {
     x[t] = sh.v1[t];
     mu[t] = sh.v3[t];
@@ -62,8 +64,12 @@ int main(int argc, char** argv) {
     std::vector<double> in((size_t)NY * NY + 2 * NY), out(2 * NY + NY * NY + 2 * NY, 0.0), ws((size_t)BK_NP * BK_NP, 0.0);
     if (!read_all(argv[2], in)) return 4;
     const double* A = in.data();
+    const int lus = argc > 4 ? atoi(argv[4]) : 0;
     emu::run_grid(1, [&] {
-      lu_kernel(A, A + NY * NY, A + NY * NY + NY, out.data(), out.data() + NY, ws.data(), out.data() + 2 * NY);
+      if (lus == 0)
+        lu_kernel<0>(A, A + NY * NY, A + NY * NY + NY, out.data(), out.data() + NY, ws.data(), out.data() + 2 * NY);
+      else
+        lu_kernel<1>(A, A + NY * NY, A + NY * NY + NY, out.data(), out.data() + NY, ws.data(), out.data() + 2 * NY);
     }, BK_T);
     FILE* f = fopen(argv[3], "wb");
     fwrite(out.data(), 8, out.size(), f);
@@ -137,6 +143,10 @@ int main(int argc, char** argv) {
   const double dt = atof(argv[4]);
   const int n_steps = atoi(argv[5]);
   const unsigned grid = argc > 8 ? (unsigned)atoi(argv[8]) : 2u;
+  const int lus = argc > 9 ? atoi(argv[9]) : 0;   // LU strategy (1: the LDS-panel kernels)
+#if !BK_LDS_F
+  if (lus != 0) return 6;
+#endif
   std::vector<double> in((size_t)NY * ld + NR);
   if (!read_all(argv[6], in)) return 4;
   std::vector<double> y(in.begin(), in.begin() + (size_t)NY * ld), lnA(in.begin() + (size_t)NY * ld, in.end());
@@ -150,13 +160,25 @@ int main(int argc, char** argv) {
   long long coll;
   if (!strcmp(which, "be"))
     coll = emu::run_grid(grid, [&] {
-      chem_k_be_persistent(n, ld, y.data(), lnA.data(), o, status.data(), counters.data(), &queue, ws.data(), 0,
-                           nullptr, nullptr);
+      if (lus == 0)
+        chem_k_be_persistent(n, ld, y.data(), lnA.data(), o, status.data(), counters.data(), &queue, ws.data(), 0,
+                             nullptr, nullptr);
+#if BK_LDS_F
+      else
+        chem_k_be_persistent_lup(n, ld, y.data(), lnA.data(), o, status.data(), counters.data(), &queue, ws.data(),
+                                 0, nullptr, nullptr);
+#endif
     }, BK_T);
   else if (!strcmp(which, "ros2"))
     coll = emu::run_grid(grid, [&] {
-      chem_k_ros2_persistent(n, ld, y.data(), lnA.data(), o, status.data(), counters.data(), &queue, ws.data(), 0, 0,
-                             nullptr, nullptr, nullptr);
+      if (lus == 0)
+        chem_k_ros2_persistent(n, ld, y.data(), lnA.data(), o, status.data(), counters.data(), &queue, ws.data(), 0,
+                               0, nullptr, nullptr, nullptr);
+#if BK_LDS_F
+      else
+        chem_k_ros2_persistent_lup(n, ld, y.data(), lnA.data(), o, status.data(), counters.data(), &queue,
+                                   ws.data(), 0, 0, nullptr, nullptr, nullptr);
+#endif
     }, BK_T);
   else {
     // "ros2p": the library's Rosenbrock sequence with a probe budget of 48 attempts: probe launch,

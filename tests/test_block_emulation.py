@@ -10,12 +10,13 @@ exit status 9.  Lanes run one after another between collectives, so a lane that 
 lane of its wave wrote without a wave barrier in between reads the old value and the results
 diverge from the reference.  The build adds UBSan.
 
-Checked: the MFMA-tiled LU with the two triangular solves (G x = b, G^T mu = lam) against LAPACK
-for the 53-species (factors in LDS) and 150-species (factors in the device workspace) sizes,
+Checked: both LU strategies (register panel, LDS panel) with their triangular solves (G x = b,
+G^T mu = lam) against LAPACK for the 53-species (factors in LDS) and 150-species (factors in the
+device workspace, LDS panel only) sizes,
 including a matrix whose first column is tiny (pivoting); backward Euler and the adaptive
 Rosenbrock method against the oracle (equal step sequences, states within 1e-8) on the 53-species
 mechanism (also the 24-cell, 6 x 1e-8 s configuration, several workgroups on one queue) and on the
-30-species SRI/P-log mechanism at both P-log pressure intervals; the source-term and Jacobian
+30-species SRI/P-log mechanism at both P-log pressure intervals, also with the LDS-panel kernels; the source-term and Jacobian
 kernels of the 150-species mechanism against the oracle (1e-12 of the term magnitudes) and its
 fixed-step Rosenbrock integration; the backward-Euler discrete adjoint (tape, segment recompute,
 halved steps) of all three mechanisms against the oracle's reverse sweep (1e-6).
@@ -80,8 +81,8 @@ def _run(cmd, timeout=900):
     assert r.returncode == 0, f"emulation failed ({r.returncode}): {r.stderr[-2000:]}"
 
 
-@pytest.mark.parametrize("name", ["ch4like_53_325", "large_150_1000"])
-def test_block_lu_and_solves_match_lapack(generator, tmp_path_factory, name):
+@pytest.mark.parametrize("name,lus", [("ch4like_53_325", 0), ("ch4like_53_325", 1), ("large_150_1000", 1)])
+def test_block_lu_and_solves_match_lapack(generator, tmp_path_factory, name, lus):
     exe, d, om = _driver(generator, tmp_path_factory, name)
     ny = om.n
     rng = np.random.default_rng(7)
@@ -95,7 +96,7 @@ def test_block_lu_and_solves_match_lapack(generator, tmp_path_factory, name):
         fin, fout = os.path.join(d, "lu_in.bin"), os.path.join(d, "lu_out.bin")
         with open(fin, "wb") as f:
             f.write(np.concatenate([A.ravel(), b, lam]).astype("<f8").tobytes())
-        _run([exe, "lu", fin, fout])
+        _run([exe, "lu", fin, fout, str(lus)])
         out = np.frombuffer(open(fout, "rb").read(), "<f8")
         x, mu = out[:ny], out[ny:2 * ny]
         xr, mr = np.linalg.solve(A, b), np.linalg.solve(A.T, lam)
@@ -105,7 +106,7 @@ def test_block_lu_and_solves_match_lapack(generator, tmp_path_factory, name):
         assert np.abs(mu - mr).max() <= bound * np.abs(mr).max()
 
 
-def _integrate(generator, tmp_path_factory, name, which, cfg, nc, dt, n_steps, ld_pad=3, grid=2):
+def _integrate(generator, tmp_path_factory, name, which, cfg, nc, dt, n_steps, ld_pad=3, grid=2, lus=0):
     exe, d, om = _driver(generator, tmp_path_factory, name)
     T, p, Y = sample_config(cfg, om.ns, nc)
     if any(rx.kind == "plog" for rx in om.reactions):
@@ -118,7 +119,7 @@ def _integrate(generator, tmp_path_factory, name, which, cfg, nc, dt, n_steps, l
     with open(fin, "wb") as f:
         f.write(ys.astype("<f8").tobytes())
         f.write(np.asarray(om.lnA_default, "<f8").tobytes())
-    _run([exe, which, str(nc), str(ld), repr(dt), str(n_steps), fin, fout, str(grid)])
+    _run([exe, which, str(nc), str(ld), repr(dt), str(n_steps), fin, fout, str(grid), str(lus)])
     raw = open(fout, "rb").read()
     k = 8 * om.n * ld
     y = np.frombuffer(raw[:k], "<f8").reshape(om.n, ld)[:, :nc].T
@@ -127,9 +128,9 @@ def _integrate(generator, tmp_path_factory, name, which, cfg, nc, dt, n_steps, l
     return om, y0, y, st, cnt
 
 
-@pytest.mark.parametrize("name", ["ch4like_53_325", "mix_30_90"])
-def test_block_backward_euler_matches_oracle(generator, tmp_path_factory, name):
-    om, y0, y, st, cnt = _integrate(generator, tmp_path_factory, name, "be", "be_small", 3, 2e-8, 2)
+@pytest.mark.parametrize("name,lus", [("ch4like_53_325", 0), ("mix_30_90", 0), ("ch4like_53_325", 1)])
+def test_block_backward_euler_matches_oracle(generator, tmp_path_factory, name, lus):
+    om, y0, y, st, cnt = _integrate(generator, tmp_path_factory, name, "be", "be_small", 3, 2e-8, 2, lus=lus)
     ref = oracle.integrate_be(om, y0, 2e-8, 2)
     np.testing.assert_array_equal(st, ref["status"])
     np.testing.assert_array_equal(cnt[0], ref["steps"])
@@ -149,9 +150,9 @@ def test_block_backward_euler_recorded_geometry(generator, tmp_path_factory):
     assert integrated_state_error(om, y, ref["y"]).max() <= 1e-8
 
 
-@pytest.mark.parametrize("name", ["ch4like_53_325", "mix_30_90"])
-def test_block_rosenbrock_matches_oracle(generator, tmp_path_factory, name):
-    om, y0, y, st, cnt = _integrate(generator, tmp_path_factory, name, "ros2", "ros2_methane", 3, 1e-9, 0)
+@pytest.mark.parametrize("name,lus", [("ch4like_53_325", 0), ("mix_30_90", 0), ("mix_30_90", 1)])
+def test_block_rosenbrock_matches_oracle(generator, tmp_path_factory, name, lus):
+    om, y0, y, st, cnt = _integrate(generator, tmp_path_factory, name, "ros2", "ros2_methane", 3, 1e-9, 0, lus=lus)
     ref = oracle.integrate_ros2(om, y0, 1e-9)
     np.testing.assert_array_equal(st, ref["status"])
     np.testing.assert_array_equal(cnt[0], ref["accepted"])

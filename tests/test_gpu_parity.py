@@ -242,3 +242,57 @@ def test_block_form_refuses_plain_and_tape(mechs):
     with pytest.raises(ChemError, match="tape"):
         gm.chem_integrate(8, 8, y, None, default_options(method=1, dt=1e-8), Tape(gm, 8, 1, method=1, max_steps=16),
                           st, None)
+
+
+def test_lu_strategies(mechs):
+    """LU strategy 1 (LDS-panel LU, blocked solves) of the block form with the factors in LDS:
+    backward Euler and Rosenbrock against the oracle on the bars of the tests above; the strategy
+    is kept per method, reported back, refused where its kernels do not exist, and chosen by
+    chem_autotune together with the launch shape."""
+    import torch
+    from paper_2510_10005_amd import CHEM_BE, CHEM_PERSISTENT, CHEM_ROS2, default_options
+    from paper_2510_10005_amd._binding import ChemError
+    gm, om = mechs
+    if om.n <= 24 or om.n > 64:
+        with pytest.raises(ChemError, match="LU strategy 1"):
+            gm.chem_set_lu_strategy(CHEM_ROS2, 1)
+        assert gm.chem_get_lu_strategy(CHEM_ROS2) == 0
+        return
+    with pytest.raises(ChemError):
+        gm.chem_set_lu_strategy(CHEM_ROS2, 2)
+    for method in (CHEM_BE, CHEM_ROS2):
+        gm.chem_set_lu_strategy(method, 1)
+        assert gm.chem_get_lu_strategy(method) == 1
+    try:
+        nc = 24
+        T, p, Y = sample_config("be_small", om.ns, nc)
+        y0 = oracle.state_from_TPY(om, T, p, Y)
+        ref = oracle.integrate_be(om, y0, 6e-8, 6)
+        got, st, cnt = _integrate_gpu(gm, om, y0, default_options(method=CHEM_BE, dt=6e-8, n_steps=6), ld=nc + 5)
+        np.testing.assert_array_equal(st, ref["status"])
+        np.testing.assert_array_equal(cnt[0], ref["steps"])
+        e_be = integrated_state_error(om, got, ref["y"]).max()
+        T, p, Y = sample_config("ros2_1m", om.ns, 16)
+        y0 = oracle.state_from_TPY(om, T, p, Y)
+        ref = oracle.integrate_ros2(om, y0, 2e-8)
+        got, st, cnt = _integrate_gpu(gm, om, y0, default_options(method=CHEM_ROS2, dt=2e-8, n_steps=0))
+        np.testing.assert_array_equal(st, ref["status"])
+        same = (cnt[0] == ref["accepted"]) & (cnt[1] == ref["rejected"])
+        e_r = integrated_state_error(om, got, ref["y"])
+        print(f"[gpu] LU strategy 1: BE max rel err {e_be:.2e}; ROS2 {np.count_nonzero(~same)} of 16 cells with a "
+              f"different step sequence, max rel err on the rest {e_r[same].max() if same.any() else 0:.2e}",
+              flush=True)
+        assert e_be <= 1e-8
+        assert np.count_nonzero(~same) <= 1 and e_r[same].max() <= 1e-8
+        # autotuning picks the strategy with the launch shape
+        n = 512
+        T, p, Y = sample_config("ros2_1m", om.ns, n)
+        yd = dev_soa(oracle.state_from_TPY(om, T, p, Y), n)
+        gm.chem_autotune(n, n, yd, None, default_options(method=CHEM_ROS2, dt=2e-8, n_steps=0, form=CHEM_PERSISTENT))
+        assert gm.chem_get_lu_strategy(CHEM_ROS2) in (0, 1)
+        print(f"[gpu] autotune: LU strategy {gm.chem_get_lu_strategy(CHEM_ROS2)}, launch "
+              f"{gm.chem_get_launch(CHEM_ROS2, CHEM_PERSISTENT)}", flush=True)
+        torch.cuda.synchronize()
+    finally:
+        for method in (CHEM_BE, CHEM_ROS2):
+            gm.chem_set_lu_strategy(method, 0)
