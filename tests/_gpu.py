@@ -54,3 +54,15 @@ def integrated_state_error(om, got, ref):
     eT = np.abs(got[:, 0] - ref[:, 0]) / np.abs(ref[:, 0])
     eY = np.abs(Yg - Yr) / np.maximum(np.abs(Yr), 1e-12)
     return np.concatenate([eT[:, None], eY], axis=1)
+
+
+def gradient_errors(got, ref, floor=1e-3):
+    """Errors of gradient arrays [cells, k]: (largest error relative to each column's largest
+    |ref|, largest element-wise relative error over the entries with |ref| >= floor x that column
+    maximum)."""
+    scale = np.abs(ref).max(axis=0, keepdims=True)
+    scale = np.where(scale > 0, scale, 1.0)
+    col = (np.abs(got - ref) / scale).max()
+    big = np.abs(ref) >= floor * scale
+    elem = (np.abs(got - ref)[big] / np.abs(ref)[big]).max() if big.any() else 0.0
+    return float(col), float(elem)

@@ -4,7 +4,8 @@ The persistent form of chem_integrate issues two kernels (queue reset, integrato
 allocation once its buffers exist, so it can be captured.  Each replay re-integrates the same
 initial states; every replay must reproduce the eager call bit for bit (cells are independent and
 each lane runs the same instruction sequence), with eager work and synchronisations between the
-replays.
+replays.  Both the register form (10 species) and the block form (53 species, one cell per
+workgroup, probe/resume schedule) are captured.
 """
 
 import numpy as np
@@ -18,12 +19,12 @@ from _gpu import gpu_mechanism
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("method", ["ros2", "be"])
-def test_graph_replay_matches_eager(method):
+@pytest.mark.parametrize("mech,method,n", [("h2like_10_27", "ros2", 6000), ("h2like_10_27", "be", 6000),
+                                           ("ch4like_53_325", "ros2", 600), ("ch4like_53_325", "be", 600)])
+def test_graph_replay_matches_eager(mech, method, n):
     from paper_2510_10005_amd import CHEM_BE, CHEM_PERSISTENT, CHEM_ROS2, default_options
-    gm, om = gpu_mechanism("h2like_10_27")
+    gm, om = gpu_mechanism(mech)
     cfg = STATE_CONFIGS["ros2_1m"]
-    n = 6000
     T, p, Y = sample_states(om.ns, n, cfg.seed, cfg.T_range, cfg.alpha, cfg.p)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     y0 = torch.empty((om.n, n), dtype=torch.float64, device="cuda")

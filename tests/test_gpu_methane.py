@@ -11,7 +11,8 @@ oracle needs minutes per cell at these horizons, so its results are stored rathe
   sampled cells and on the first 64 cells (zero elsewhere; the adjoint is linear in it): dL/dy0 of
   the 3 cells against the oracle's discrete adjoint and of the 64 cells against the oracle's
   tangent (forward-sensitivity) reference, dL/dlnA summed over the 67 cells against both, all
-  within 1e-6;
+  within 1e-6 of each column's largest entry and element by element on the entries of at least
+  1e-3 of it;
 * the same adjoint on the first 64 cells against central differences (h = 1e-6) of the GPU
   forward on 32 ln A_j sampled with seed 4000.
 """
@@ -27,7 +28,7 @@ import oracle
 from oracle.sensitivity import final_loss
 from synth.states import STATE_CONFIGS, loss_weights, sample_states
 
-from _gpu import gpu_mechanism, integrated_state_error
+from _gpu import gpu_mechanism, gradient_errors, integrated_state_error
 
 pytestmark = pytest.mark.gpu
 
@@ -115,16 +116,17 @@ def test_methane_adjoint_fullsize_vs_oracle_adjoint_and_tangent(methane):
     d0 = out.cpu().numpy().T
     gg = g.cpu().numpy()
 
-    def rel_cols(a, b):
-        scale = np.abs(b).max(axis=0, keepdims=True)
-        return (np.abs(a - b) / np.where(scale > 0, scale, 1.0)).max()
-    e_adj = rel_cols(d0[ia], np.array([a["dLdy0"] for a in adj]))
-    e_tan = rel_cols(d0[it], np.array(ref["tangent"]["dLdy0"]))
+    e_adj, el_adj = gradient_errors(d0[ia], np.array([a["dLdy0"] for a in adj]))
+    e_tan, el_tan = gradient_errors(d0[it], np.array(ref["tangent"]["dLdy0"]))
     g_ref = np.array(ref["adjoint"]["dLdlnA_sum"]) + np.array(ref["tangent"]["dLdlnA_sum"])
     e_g = np.abs(gg - g_ref).max() / np.abs(g_ref).max()
-    print(f"[gpu] 53-species adjoint: dL/dy0 vs oracle adjoint {e_adj:.2e}, vs oracle tangent {e_tan:.2e}; "
-          f"dL/dlnA {e_g:.2e}", flush=True)
+    big = np.abs(g_ref) >= 1e-3 * np.abs(g_ref).max()
+    el_g = (np.abs(gg - g_ref)[big] / np.abs(g_ref)[big]).max()
+    print(f"[gpu] 53-species adjoint: dL/dy0 vs oracle adjoint {e_adj:.2e} (element-wise {el_adj:.2e}), vs oracle "
+          f"tangent {e_tan:.2e} ({el_tan:.2e}); dL/dlnA {e_g:.2e} ({el_g:.2e})", flush=True)
     assert e_adj <= 1e-6 and e_tan <= 1e-6 and e_g <= 1e-6
+    # element by element on the entries of at least 1e-3 of their column's (dL/dlnA: vector's) largest
+    assert el_adj <= 1e-6 and el_tan <= 1e-6 and el_g <= 1e-6
 
 
 def test_methane_adjoint_vs_central_differences(methane):

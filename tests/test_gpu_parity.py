@@ -15,7 +15,7 @@ import pytest
 import oracle
 from synth.states import paper_sampler, sample_config
 
-from _gpu import dev_soa, empty, gpu_mechanism, host_aos, integrated_state_error
+from _gpu import dev_soa, empty, gpu_mechanism, gradient_errors, host_aos, integrated_state_error
 
 pytestmark = pytest.mark.gpu
 
@@ -213,12 +213,16 @@ def test_be_adjoint(mechs):
     gm.chem_integrate_adjoint(tape, None, lam_d, out, g)
     torch.cuda.synchronize()
     lam0 = host_aos(out, nc)[ok]
-    scale = np.abs(lam0_ref).max(axis=0, keepdims=True)
-    e0 = np.abs(lam0 - lam0_ref) / np.where(scale > 0, scale, 1.0)
+    e0, el0 = gradient_errors(lam0, lam0_ref)
     gs = g_ref.sum(axis=0)
-    eg = np.abs(g.cpu().numpy() - gs) / np.abs(gs).max()
-    print(f"[gpu] BE adjoint: dL/dy0 max rel err {e0.max():.2e}, dL/dlnA max rel err {eg.max():.2e}", flush=True)
-    assert e0.max() <= 1e-6 and eg.max() <= 1e-6
+    gg = g.cpu().numpy()
+    eg = np.abs(gg - gs).max() / np.abs(gs).max()
+    big = np.abs(gs) >= 1e-3 * np.abs(gs).max()
+    elg = (np.abs(gg - gs)[big] / np.abs(gs)[big]).max()
+    print(f"[gpu] BE adjoint: dL/dy0 max rel err {e0:.2e} (element-wise {el0:.2e}), dL/dlnA {eg:.2e} "
+          f"(element-wise {elg:.2e})", flush=True)
+    assert e0 <= 1e-6 and eg <= 1e-6
+    assert el0 <= 1e-6 and elg <= 1e-6      # entries of at least 1e-3 of their column's largest
     # determinism: a second run gives bitwise the same gradient
     g2 = torch.zeros_like(g)
     gm.chem_integrate_adjoint(tape, None, lam_d, out, g2)

@@ -9,7 +9,8 @@ terms change the gradient by percents), both energy modes, segments that end mid
 (bitwise equal to a single launch), a tape capacity below some cells' step counts (those cells
 stop with status 3 and get a zero adjoint), and bitwise-reproducible gradients.
 Tolerance 1e-6 relative (dL/dy0 per component against the largest |value| of that component
-over the cells; dL/dlnA against its largest |value|).
+over the cells, and element by element on the entries of at least 1e-3 of it; dL/dlnA against
+its largest |value|).
 """
 
 import numpy as np
@@ -20,7 +21,7 @@ import oracle
 from oracle.sensitivity import final_loss, ros2_adjoint
 from synth.states import loss_weights, sample_config
 
-from _gpu import dev_soa, empty, gpu_mechanism, host_aos, integrated_state_error
+from _gpu import dev_soa, empty, gpu_mechanism, gradient_errors, host_aos, integrated_state_error
 
 pytestmark = pytest.mark.gpu
 
@@ -106,8 +107,10 @@ def test_ros2_adjoint_matches_oracle(mechs, case):
     print(f"[gpu] {om.ns} species, case {case}: adjoint", flush=True)
     lam0, g = _adjoint(gm, om, tape, lamN, ld)
     e0, eg = _errors(lam0, g, lam0_ref, g_ref)
-    print(f"[gpu] ROS2 adjoint {case}: dL/dy0 max rel err {e0:.2e}, dL/dlnA max rel err {eg:.2e}", flush=True)
-    assert e0 <= 1e-6 and eg <= 1e-6
+    el0 = gradient_errors(lam0, lam0_ref)[1]
+    print(f"[gpu] ROS2 adjoint {case}: dL/dy0 max rel err {e0:.2e} (element-wise on entries >= 1e-3 of the column "
+          f"maximum {el0:.2e}), dL/dlnA max rel err {eg:.2e}", flush=True)
+    assert e0 <= 1e-6 and eg <= 1e-6 and el0 <= 1e-6
     lam0b, g2 = _adjoint(gm, om, tape, lamN, ld)
     assert np.array_equal(g, g2) and np.array_equal(lam0, lam0b)
 
