@@ -31,8 +31,8 @@ resulting solution's convergence to the fixed-step reference is pinned).
 from .mechanism import Mechanism, load_mechanism  # noqa: F401
 from .thermo import nasa7_molar, thermo_mass_specific  # noqa: F401
 from .kinetics import (  # noqa: F401
-    rates_of_progress, source_terms, jacobian, jacobian_complex_step, dsource_dlnA,
-    source_sum_scale,
+    CONST_P, CONST_V, CONST_P_REACTOR, rates_of_progress, source_terms, jacobian, jacobian_complex_step,
+    dsource_dlnA, source_sum_scale,
 )
 from .integrate import (  # noqa: F401
     CELL_OK, CELL_NEWTON_FAIL, CELL_DT_UNDERFLOW, CELL_MAX_STEPS, CELL_NONFINITE, CELL_T_RANGE,

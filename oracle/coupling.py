@@ -17,15 +17,16 @@ from __future__ import annotations
 
 import numpy as np
 
-from .kinetics import CONST_P
+from .kinetics import CONST_V
 from .mechanism import R
 from .thermo import nasa7_molar
 
 
 def energy_density(mech, C, T, energy):
-    """(rho u, rho c_v) for energy == CONST_V, (rho h, rho c_p) for CONST_P; C [m, ns], T [m]."""
+    """(rho u, rho c_v) for energy == CONST_V, (rho h, rho c_p) for CONST_P and CONST_P_REACTOR;
+    C [m, ns], T [m]."""
     cp_R, h_RT, _, _, _ = nasa7_molar(mech, np.asarray(T))
-    shift = 0.0 if energy == CONST_P else 1.0
+    shift = 1.0 if energy == CONST_V else 0.0
     e = (C * (h_RT - shift)).sum(axis=1) * R * T
     de = (C * (cp_R - shift)).sum(axis=1) * R
     return e, de

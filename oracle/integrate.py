@@ -107,7 +107,7 @@ def _newton_scale(mech, y, rho, opt):
     return sc
 
 
-def be_newton(mech, y_n, dt, lnA, opt):
+def be_newton(mech, y_n, dt, lnA, opt, rho=None):
     """Solve y - y_n - dt S(y) = 0 for every cell of y_n (shape [m, n]) by full Newton.
 
     Returns (y, converged[m], iterations[m]).  Iteration k solves
@@ -115,9 +115,15 @@ def be_newton(mech, y_n, dt, lnA, opt):
     has converged when max_i |delta_i| / sc_i <= 1 (scales from y_{k+1}); it has failed
     when the scaled norm grows from iteration 2 on, when y_{k+1} is not finite or has
     T <= 0, or when ``newton_max`` iterations pass without convergence.
+
+    ``rho`` [m]: the density in the scales, by default that of y_n.  The integrators pass the
+    density of the state at the start of the integration: it is a constant of the motion in the
+    density-holding energy modes, and in the reactor mode (whose density changes) it keeps the
+    scales fixed over the call.
     """
     m, n = y_n.shape
-    rho = (y_n[:, 1:] * mech.W[None, :]).sum(axis=1)
+    if rho is None:
+        rho = (y_n[:, 1:] * mech.W[None, :]).sum(axis=1)
     y = y_n.copy()
     active = np.ones(m, dtype=bool)
     conv = np.zeros(m, dtype=bool)
@@ -155,9 +161,9 @@ def be_newton(mech, y_n, dt, lnA, opt):
     return y, conv, iters
 
 
-def _be_substep_recursive(mech, y, dt, lnA, opt, depth, record):
+def _be_substep_recursive(mech, y, dt, lnA, opt, depth, record, rho):
     """One step of size dt for a single cell, halving on Newton failure (depth-first)."""
-    ynew, conv, it = be_newton(mech, y[None], dt, lnA, opt)
+    ynew, conv, it = be_newton(mech, y[None], dt, lnA, opt, np.array([rho]))
     newton = int(it[0])
     if conv[0]:
         if record is not None:
@@ -165,11 +171,11 @@ def _be_substep_recursive(mech, y, dt, lnA, opt, depth, record):
         return ynew[0], True, newton
     if depth >= opt.halving_max_depth:
         return y, False, newton
-    ymid, ok, n1 = _be_substep_recursive(mech, y, 0.5 * dt, lnA, opt, depth + 1, record)
+    ymid, ok, n1 = _be_substep_recursive(mech, y, 0.5 * dt, lnA, opt, depth + 1, record, rho)
     newton += n1
     if not ok:
         return ymid, False, newton
-    yend, ok, n2 = _be_substep_recursive(mech, ymid, 0.5 * dt, lnA, opt, depth + 1, record)
+    yend, ok, n2 = _be_substep_recursive(mech, ymid, 0.5 * dt, lnA, opt, depth + 1, record, rho)
     return yend, ok, newton + n2
 
 
@@ -188,11 +194,12 @@ def integrate_be(mech, y0, dt_total, n_steps, lnA=None, opt=None, record=False):
     newton = np.zeros(nc, dtype=np.int64)
     traj = [[] for _ in range(nc)] if record else None
     dt = dt_total / n_steps
+    rho0 = (y[:, 1:] * mech.W[None, :]).sum(axis=1)
     for _ in range(n_steps):
         idx = np.nonzero(status == CELL_OK)[0]
         if idx.size == 0:
             break
-        ynew, conv, it = be_newton(mech, y[idx], dt, lnA, opt)
+        ynew, conv, it = be_newton(mech, y[idx], dt, lnA, opt, rho0[idx])
         newton[idx] += it
         for c, ok, yc in zip(idx, conv, ynew):
             if ok:
@@ -206,10 +213,10 @@ def integrate_be(mech, y0, dt_total, n_steps, lnA=None, opt=None, record=False):
                 continue
             # the whole step failed: split it into two halves, recursively
             rec = [] if record else None
-            y1, ok, n1 = _be_substep_recursive(mech, y[c], 0.5 * dt, lnA, opt, 1, rec)
+            y1, ok, n1 = _be_substep_recursive(mech, y[c], 0.5 * dt, lnA, opt, 1, rec, rho0[c])
             newton[c] += n1
             if ok:
-                y2, ok, n2 = _be_substep_recursive(mech, y1, 0.5 * dt, lnA, opt, 1, rec)
+                y2, ok, n2 = _be_substep_recursive(mech, y1, 0.5 * dt, lnA, opt, 1, rec, rho0[c])
                 newton[c] += n2
                 y1 = y2
             y[c] = y1

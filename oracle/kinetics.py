@@ -19,6 +19,12 @@ Definitions followed (all in SI-kmol units):
 * omega_T = -sum H_i omega_i / sum C_i Cp_i at constant pressure (Appendix B, eq.
   temperature_source_h) or -sum U_i omega_i / sum C_i Cv_i at constant volume (eq.
   temperature_source); the denominators are volumetric heat capacities.
+* constant-pressure reactor with dilatation (energy = CONST_P_REACTOR): the same omega_T, and the
+  concentrations also follow the density change.  With C_i = rho Y_i / W_i, dY_i/dt = W_i omega_i /
+  rho and rho = p Wbar / (R T) at fixed p, d ln rho / dt = -g with g = sum_j omega_j / sum_j C_j +
+  omega_T / T, so dC_i/dt = omega_i - C_i g.  (Appendix B's source terms keep dC_i/dt = omega_i,
+  i.e. they neglect this term; the reactor form keeps p = R T sum C and the mass-specific
+  enthalpy sum C_i H_i / rho constant.)
 """
 
 from __future__ import annotations
@@ -29,7 +35,7 @@ from .mechanism import R
 from .thermo import nasa7_molar
 
 LN10 = np.log(10.0)
-CONST_P, CONST_V = 0, 1
+CONST_P, CONST_V, CONST_P_REACTOR = 0, 1, 2
 
 
 def _conc_product(C, stoich):
@@ -239,13 +245,25 @@ def rates_of_progress(mech, y, lnA=None):
 
 def _temperature_weights(h_RT, cp_R, energy):
     """(enthalpy-like weights H_i/RT, heat-capacity weights Cp_i/R) for the chosen energy mode."""
-    if energy == CONST_P:
+    if energy in (CONST_P, CONST_P_REACTOR):
         return h_RT, cp_R
     return h_RT - 1.0, cp_R - 1.0   # U/RT = H/RT - 1, Cv/R = Cp/R - 1
 
 
+def _dilatation_rate(S0, T, C):
+    """g = sum_j omega_j / sum_j C_j + omega_T / T (so that d ln rho/dt = -g at constant p)."""
+    return S0[:, 1:].sum(axis=1) / C.sum(axis=1) + S0[:, 0] / T
+
+
 def source_terms(mech, y, lnA=None, energy=CONST_P):
-    """S(y) = (omega_T, omega_1..omega_ns), shape [nc, n]."""
+    """S(y) = (omega_T, omega_1..omega_ns), shape [nc, n]; for CONST_P_REACTOR the species
+    entries are omega_i - C_i g."""
+    if energy == CONST_P_REACTOR:
+        yy, T, C, _ = _prepare(mech, y, lnA)
+        S0 = source_terms(mech, y, lnA, CONST_P)
+        S = S0.copy()
+        S[:, 1:] -= C * _dilatation_rate(S0, T, C)[:, None]
+        return S
     y, T, C, lnA = _prepare(mech, y, lnA)
     q, _, _, th = rates_of_progress(mech, y, lnA)
     cp_R, h_RT = th[0], th[1]
@@ -273,6 +291,10 @@ def source_sum_scale(mech, y, lnA=None, energy=CONST_P):
     hw, cw = _temperature_weights(h_RT, cp_R, energy)
     D = (C * cw).sum(axis=1)
     magT = np.abs(T) * (np.abs(hw) * mag).sum(axis=1) / np.abs(D)
+    if energy == CONST_P_REACTOR:
+        # the dilatation term C_i g sums the species rates and omega_T / T
+        gm = mag.sum(axis=1) / np.abs(C.sum(axis=1)) + magT / np.abs(T)
+        mag = mag + np.abs(C) * gm[:, None]
     return np.concatenate([magT[:, None], mag], axis=1)
 
 
@@ -285,7 +307,35 @@ def jacobian(mech, y, lnA=None, energy=CONST_P, magnitude=False):
 
     With ``magnitude`` also returns M (same shape): every entry recomputed with the absolute
     value of each term it sums, the scale that bounds the rounding error of that entry.
+
+    CONST_P_REACTOR: the species rows of dS/dy for S_i = omega_i - C_i g are J_ik - delta_ik g -
+    C_i dg/dy_k with dg/dy_k = (sum_j J_jk) / sum C - [k >= 1] sum omega / (sum C)^2 + J_0k / T -
+    [k = 0] omega_T / T^2 (J: the constant-pressure Jacobian, sums over the species rows).
     """
+    if energy == CONST_P_REACTOR:
+        yy, T, C, _ = _prepare(mech, y, lnA)
+        res = jacobian(mech, y, lnA, CONST_P, magnitude)
+        J0, M0 = res if magnitude else (res, None)
+        S0 = source_terms(mech, y, lnA, CONST_P)
+        c, Om = C.sum(axis=1), S0[:, 1:].sum(axis=1)
+        g = Om / c + S0[:, 0] / T
+        dg = J0[:, 1:, :].sum(axis=1) / c[:, None] + J0[:, 0, :] / T[:, None]
+        dg[:, 1:] -= (Om / c ** 2)[:, None]
+        dg[:, 0] -= S0[:, 0] / T ** 2
+        J = J0.copy()
+        J[:, 1:, :] -= C[:, :, None] * dg[:, None, :]
+        J[:, 1:, 1:] -= g[:, None, None] * np.eye(mech.ns)[None]
+        if not magnitude:
+            return J
+        sc = source_sum_scale(mech, y, lnA, CONST_P)
+        gm = sc[:, 1:].sum(axis=1) / np.abs(c) + sc[:, 0] / np.abs(T)
+        dgm = M0[:, 1:, :].sum(axis=1) / np.abs(c)[:, None] + M0[:, 0, :] / np.abs(T)[:, None]
+        dgm[:, 1:] += (sc[:, 1:].sum(axis=1) / c ** 2)[:, None]
+        dgm[:, 0] += sc[:, 0] / T ** 2
+        Mg = M0.copy()
+        Mg[:, 1:, :] += np.abs(C)[:, :, None] * dgm[:, None, :]
+        Mg[:, 1:, 1:] += gm[:, None, None] * np.eye(mech.ns)[None]
+        return J, Mg
     y, T, C, lnA = _prepare(mech, y, lnA)
     nc, n, ns = y.shape[0], mech.n, mech.ns
     lnT = np.log(T)
@@ -366,7 +416,15 @@ def jacobian_complex_step(mech, y, lnA=None, energy=CONST_P, h=1e-40):
 
 def dsource_dlnA(mech, y, lnA=None, energy=CONST_P):
     """dS/d lnA_j, shape [nc, n, nr]: lnA_j scales k_f and k_r (and k_0, k_inf) alike, so
-    d q_j / d lnA_j = q_j, d omega_i / d lnA_j = nu_ij q_j and the T row follows omega_T."""
+    d q_j / d lnA_j = q_j, d omega_i / d lnA_j = nu_ij q_j and the T row follows omega_T (with the
+    dilatation term, the species rows also subtract C_i dg/dlnA_j)."""
+    if energy == CONST_P_REACTOR:
+        yy, T, C, _ = _prepare(mech, y, lnA)
+        P = dsource_dlnA(mech, y, lnA, CONST_P)
+        dg = P[:, 1:, :].sum(axis=1) / C.sum(axis=1)[:, None] + P[:, 0, :] / T[:, None]
+        P = P.copy()
+        P[:, 1:, :] -= C[:, :, None] * dg[:, None, :]
+        return P
     y, T, C, lnA = _prepare(mech, y, lnA)
     q, _, _, th = rates_of_progress(mech, y, lnA)
     cp_R, h_RT = th[0], th[1]
