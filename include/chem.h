@@ -64,7 +64,7 @@ enum {
 enum { CHEM_BE = 0, CHEM_ROS2 = 1, CHEM_SDIRK2 = 2, CHEM_SDIRK4 = 3, CHEM_YASS = 4 };
 enum { CHEM_LINSOLVE_LU = 0, CHEM_LINSOLVE_GMRES = 1 };
 enum { CHEM_PRECOND_NONE = 0, CHEM_PRECOND_JACOBI = 1, CHEM_PRECOND_GAUSS_SEIDEL = 2 };
-enum { CHEM_CONST_P = 0, CHEM_CONST_V = 1 };
+enum { CHEM_CONST_P = 0, CHEM_CONST_V = 1, CHEM_CONST_P_REACTOR = 2 };
 enum { CHEM_PERSISTENT = 0, CHEM_PLAIN = 1 };
 enum { CHEM_FLAG_CHECK_CELLS = 1 };  /* synchronise and return CHEM_ECELLS if a cell failed */
 
@@ -107,6 +107,12 @@ enum { CHEM_FLAG_CHECK_CELLS = 1 };  /* synchronise and return CHEM_ECELLS if a 
  *                    iterations (0 with LU).
  *  energy   CHEM_CONST_P: omega_T = -sum H_i omega_i / sum C_i Cp_i (Appendix B)
  *           CHEM_CONST_V: omega_T = -sum U_i omega_i / sum C_i Cv_i (Section 3)
+ *           CHEM_CONST_P_REACTOR: the constant-pressure reactor with its density change (the
+ *           omega_T of CHEM_CONST_P, species sources omega_i - C_i g; see chem_source_terms).
+ *           Backward Euler and Rosenbrock of mechanisms with n > 24 only, without tapes
+ *           (CHEM_EUNSUPPORTED otherwise: the other integrators solve the reduced system of the
+ *           species that take part in reactions, which holds the inert species fixed, while the
+ *           reactor's expansion changes every concentration).
  *  form     CHEM_PERSISTENT: one persistent kernel, cells pulled from a work queue lane by lane.
  *           CHEM_PLAIN: one kernel launch per substep (BE: per full step) over all cells.
  *  Newton convergence: max_i |delta_i| / sc_i <= 1 with sc_T = newton_rtol T + newton_atol_T and,
@@ -213,7 +219,8 @@ chem_err chem_thermo(const chem_mech* mech, int64_t n_cells, int64_t ld, const d
  * Newton equation printed just before it fixes the sign used here.)
  * C[ns][ld] (kmol/m^3; e.g. the species rows of a state array y + ld), e[ld] (J/m^3) and T0[ld]
  * (K, the initial guess) in; T[ld] out (T may alias T0).  n_iter >= 1.  No per-cell checks: a
- * non-positive or non-finite result propagates.  CHEM_EINVAL for null pointers or a bad mode. */
+ * non-positive or non-finite result propagates.  CHEM_CONST_P_REACTOR is the enthalpy form of
+ * CHEM_CONST_P.  CHEM_EINVAL for null pointers or a bad mode. */
 chem_err chem_T_from_energy(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* C, const double* e,
                             const double* T0, int energy, int n_iter, double* T, void* stream);
 
@@ -223,11 +230,19 @@ chem_err chem_T_from_energy(const chem_mech* mech, int64_t n_cells, int64_t ld, 
 chem_err chem_cfd_source(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* y_n, const double* y_np1,
                          double dt, double* R, void* stream);
 
-/* Source term S(y) (eq. extracted_problem): dydt[n][ld] from y[n][ld]. */
+/* Source term S(y) (eq. extracted_problem): dydt[n][ld] from y[n][ld].
+ * energy CHEM_CONST_P / CHEM_CONST_V: (omega_T, omega_1..omega_ns) as in Section 3 and Appendix B
+ * (dC_i/dt = omega_i: the density is held, so p = R T sum C drifts).
+ * energy CHEM_CONST_P_REACTOR: the homogeneous reactor at fixed pressure.  C_i = rho Y_i / W_i with
+ * dY_i/dt = W_i omega_i / rho and rho = p Wbar / (R T) gives d ln rho / dt = -g,
+ *   g = sum_i omega_i / sum_i C_i + omega_T / T,   dC_i/dt = omega_i - C_i g,
+ * and omega_T as for CHEM_CONST_P; R T sum C and sum C_i H_i / rho stay constant along it. */
 chem_err chem_source_terms(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* y,
                            const double* lnA, int energy, double* dydt, void* stream);
 
-/* Analytic Jacobian dS/dy (eq. derivative_matrices_temp_evol): jac[n*n][ld], row-major i*n+j. */
+/* Analytic Jacobian dS/dy (eq. derivative_matrices_temp_evol): jac[n*n][ld], row-major i*n+j.
+ * For CHEM_CONST_P_REACTOR the species rows are J_ik - delta_ik g - C_i dg/dy_k (J: the
+ * CHEM_CONST_P Jacobian; dg/dy_k from the column sums of its species rows and its T row). */
 chem_err chem_jacobian(const chem_mech* mech, int64_t n_cells, int64_t ld, const double* y,
                        const double* lnA, int energy, double* jac, void* stream);
 

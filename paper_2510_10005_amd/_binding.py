@@ -18,7 +18,7 @@ CHEM_OK = 0
 CHEM_BE, CHEM_ROS2, CHEM_SDIRK2, CHEM_SDIRK4, CHEM_YASS = 0, 1, 2, 3, 4
 CHEM_LINSOLVE_LU, CHEM_LINSOLVE_GMRES = 0, 1
 CHEM_PRECOND_NONE, CHEM_PRECOND_JACOBI, CHEM_PRECOND_GAUSS_SEIDEL = 0, 1, 2
-CHEM_CONST_P, CHEM_CONST_V = 0, 1
+CHEM_CONST_P, CHEM_CONST_V, CHEM_CONST_P_REACTOR = 0, 1, 2
 CHEM_PERSISTENT, CHEM_PLAIN = 0, 1
 CHEM_FLAG_CHECK_CELLS = 1
 CELL_OK, CELL_NEWTON_FAIL, CELL_DT_UNDERFLOW, CELL_MAX_STEPS, CELL_NONFINITE, CELL_T_RANGE = range(6)

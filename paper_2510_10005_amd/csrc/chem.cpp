@@ -393,11 +393,24 @@ DevYassOpts yass_to_dev(const chem_integrator_opts& o) {
   return d;
 }
 
+bool known_energy(int e) { return e == CHEM_CONST_P || e == CHEM_CONST_V || e == CHEM_CONST_P_REACTOR; }
+
+// The reactor form changes every concentration (the density follows T and the mole number), so it
+// needs integrators that solve the full system: those of the block form (n > 24), without tapes.
+chem_err check_reactor(const chem_mech* M, const chem_integrator_opts* o, bool tape) {
+  if (o->energy != CHEM_CONST_P_REACTOR) return CHEM_OK;
+  if (!M->wave || (o->method != CHEM_BE && o->method != CHEM_ROS2))
+    return fail(CHEM_EUNSUPPORTED, "the constant-pressure reactor form integrates with backward Euler or "
+                "Rosenbrock for mechanisms with n > 24");
+  if (tape) return fail(CHEM_EUNSUPPORTED, "no adjoint tape for the constant-pressure reactor form");
+  return CHEM_OK;
+}
+
 chem_err validate_opts(const chem_integrator_opts* o) {
   if (!o) return fail(CHEM_EINVAL, "null options");
   if (!known_method(o->method))
     return fail(CHEM_EINVAL, "unknown method");
-  if (o->energy != CHEM_CONST_P && o->energy != CHEM_CONST_V) return fail(CHEM_EINVAL, "unknown energy mode");
+  if (!known_energy(o->energy)) return fail(CHEM_EINVAL, "unknown energy mode");
   if (o->form != CHEM_PERSISTENT && o->form != CHEM_PLAIN) return fail(CHEM_EINVAL, "unknown form");
   if (!(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(CHEM_EINVAL, "dt must be positive and finite");
   if (o->n_steps < 0) return fail(CHEM_EINVAL, "n_steps must be >= 0");
@@ -622,7 +635,7 @@ chem_err chem_T_from_energy(const chem_mech* M, int64_t n, int64_t ld, const dou
                             const double* T0, int energy, int n_iter, double* T, void* stream) {
   if (!M || !C || !e || !T0 || !T) return fail(CHEM_EINVAL, "null argument");
   if (chem_err err = check_cells(n, ld)) return err;
-  if (energy != CHEM_CONST_P && energy != CHEM_CONST_V) return fail(CHEM_EINVAL, "unknown energy mode");
+  if (!known_energy(energy)) return fail(CHEM_EINVAL, "unknown energy mode");
   if (n_iter < 1) return fail(CHEM_EINVAL, "n_iter must be >= 1");
   void* args[] = {&n, &ld, &C, &e, &T0, &energy, &n_iter, &T};
   return launch(M, K_T_FROM_ENERGY, blocks_for(n, 256), 256, static_cast<hipStream_t>(stream), args);
@@ -642,7 +655,7 @@ chem_err chem_source_terms(const chem_mech* M, int64_t n, int64_t ld, const doub
                            double* dydt, void* stream) {
   if (!M || !y || !dydt) return fail(CHEM_EINVAL, "null argument");
   if (chem_err e = check_cells(M, n, ld)) return e;
-  if (energy != CHEM_CONST_P && energy != CHEM_CONST_V) return fail(CHEM_EINVAL, "unknown energy mode");
+  if (!known_energy(energy)) return fail(CHEM_EINVAL, "unknown energy mode");
   const double* la = lnA ? lnA : M->lnA_default.as<double>();
   void* args[] = {&n, &ld, &y, &la, &energy, &dydt};
   if (M->wave && !M->wave_api)  // one cell per workgroup
@@ -654,7 +667,7 @@ chem_err chem_jacobian(const chem_mech* M, int64_t n, int64_t ld, const double* 
                        double* jac, void* stream) {
   if (!M || !y || !jac) return fail(CHEM_EINVAL, "null argument");
   if (chem_err e = check_cells(M, n, ld)) return e;
-  if (energy != CHEM_CONST_P && energy != CHEM_CONST_V) return fail(CHEM_EINVAL, "unknown energy mode");
+  if (!known_energy(energy)) return fail(CHEM_EINVAL, "unknown energy mode");
   const double* la = lnA ? lnA : M->lnA_default.as<double>();
   void* args[] = {&n, &ld, &y, &la, &energy, &jac};
   if (M->wave) {
@@ -815,6 +828,7 @@ chem_err integrate_impl(chem_mech* M, int64_t n, int64_t ld, double* y, const do
   if (!M || !y || !status) return fail(CHEM_EINVAL, "null argument");
   if (chem_err e = check_cells(M, n, ld)) return e;
   if (chem_err e = validate_opts(opts)) return e;
+  if (chem_err e = check_reactor(M, opts, tape != nullptr)) return e;
   if (M->wave) {
     // the block form (n > 24): backward Euler and Rosenbrock, persistent form; adjoint tapes for
     // backward Euler only
@@ -1170,6 +1184,7 @@ chem_err chem_autotune(chem_mech* M, int64_t n, int64_t ld, const double* y, con
   if (chem_err e = check_cells(M, n, ld)) return e;
   if (chem_err e = validate_opts(opts)) return e;
   if (opts->form != CHEM_PERSISTENT) return fail(CHEM_EUNSUPPORTED, "autotuning covers the persistent form");
+  if (chem_err e = check_reactor(M, opts, false)) return e;
   if (M->wave && opts->method != CHEM_BE && opts->method != CHEM_ROS2)
     return fail(CHEM_EUNSUPPORTED, std::string(method_name(opts->method)) + " is implemented for n <= 24");
   if (n == 0) return CHEM_OK;

@@ -750,7 +750,7 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
       os << "  }\n";
     }
     os << "  double hRT[NS], cpR[NS];\n  mech_thermo_hcp(T, invT, hRT, cpR);\n";
-    os << "  const double off = energy ? 1.0 : 0.0;\n  double N = 0.0, D = 0.0;\n";
+    os << "  const double off = energy == 1 ? 1.0 : 0.0;\n  double N = 0.0, D = 0.0;\n";
     os << "#pragma unroll\n  for (int i = 0; i < NS; ++i) {\n    N = fma(hRT[i] - off, w[i], N);\n"
           "    D = fma(C[i], cpR[i] - off, D);\n  }\n";
     os << "  S[0] = -T * N / D;\n#pragma unroll\n  for (int i = 0; i < NS; ++i) S[1 + i] = w[i];\n}\n";
@@ -786,7 +786,7 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
   }
   os << "  double cpR[NS], dcpR[NS];\n";
   os << "  if (JAC) mech_thermo_cp(T, cpR, dcpR); else mech_thermo_hcp(T, invT, hRT, cpR);\n";
-  os << "  const double off = energy ? 1.0 : 0.0;\n";
+  os << "  const double off = energy == 1 ? 1.0 : 0.0;\n";
   os << "  double hw[NS], cw[NS], N = 0.0, D = 0.0;\n";
   os << "#pragma unroll\n  for (int i = 0; i < NS; ++i) {\n    hw[i] = hRT[i] - off;\n    cw[i] = cpR[i] - off;\n"
         "    N = fma(hw[i], w[i], N);\n    D = fma(C[i], cw[i], D);\n  }\n";
@@ -825,7 +825,7 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
   os << "  double cpR[NS], hRT[NS], sR[NS], gRT[NS], dcpR[NS];\n";
   os << "  mech_thermo(T, lnT, invT, cpR, hRT, sR, gRT, dcpR);\n";
   if (any_pd) os << "  double Mc = 0.0;\n#pragma unroll\n  for (int i = 0; i < NS; ++i) Mc += C[i];\n";
-  os << "  const double off = energy ? 1.0 : 0.0;\n  double D = 0.0;\n"
+  os << "  const double off = energy == 1 ? 1.0 : 0.0;\n  double D = 0.0;\n"
         "#pragma unroll\n  for (int i = 0; i < NS; ++i) D = fma(C[i], cpR[i] - off, D);\n";
   os << "  const double muT = -T * mu[0] / D;\n";
   for (int j = 0; j < nr; ++j) {
@@ -893,7 +893,7 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
   os << "  R C[NS];\n#pragma unroll\n  for (int i = 0; i < NS; ++i) C[i] = y[1 + i];\n";
   os << "  R cpR[NS], hRT[NS], gRT[NS], dcpR[NS];\n  mech_thermo_t(T, lnT, invT, cpR, hRT, gRT, dcpR);\n";
   if (any_pd) os << "  R Mc = 0.0;\n#pragma unroll\n  for (int i = 0; i < NS; ++i) Mc += C[i];\n";
-  os << "  const double off = energy ? 1.0 : 0.0;\n  R D = 0.0;\n"
+  os << "  const double off = energy == 1 ? 1.0 : 0.0;\n  R D = 0.0;\n"
         "#pragma unroll\n  for (int i = 0; i < NS; ++i) D += C[i] * (cpR[i] - off);\n";
   os << "  const R invD = 1.0 / D;\n  const R uT = -u[0] * T * invD;\n";
   os << "  R ut[NS], w[NS];\n#pragma unroll\n  for (int i = 0; i < NS; ++i) {\n    ut[i] = u[1 + i] + uT * (hRT[i] - off);\n"

@@ -85,10 +85,11 @@ int main(int argc, char** argv) {
     if (!read_all(argv[4], in)) return 4;
     const double* y = in.data();
     const double* lnA = in.data() + (size_t)NY * ld;
-    emu::run_grid((unsigned)n, [&] { chem_k_source(n, ld, y, lnA, 0, S.data()); }, BK_T);
+    const int energy = argc > 6 ? atoi(argv[6]) : 0;
+    emu::run_grid((unsigned)n, [&] { chem_k_source(n, ld, y, lnA, energy, S.data()); }, BK_T);
     if (!strcmp(which, "jac")) {
       J.assign((size_t)n * NY * NY, 0.0);
-      emu::run_grid((unsigned)n, [&] { chem_k_jacobian(n, ld, y, lnA, 0, J.data(), 0); }, BK_T);
+      emu::run_grid((unsigned)n, [&] { chem_k_jacobian(n, ld, y, lnA, energy, J.data(), 0); }, BK_T);
     }
     FILE* f = fopen(argv[5], "wb");
     fwrite(S.data(), 8, S.size(), f);
@@ -156,7 +157,7 @@ int main(int argc, char** argv) {
   ChemOpts o{};
   o.dt = dt; o.rtol = 1e-6; o.atol = 1e-10; o.h_min = 1e-20; o.newton_rtol = 1e-10; o.newton_atol_T = 1e-8;
   o.newton_atol_Y = 1e-14; o.n_steps = n_steps; o.max_steps = 100000; o.newton_max = 10;
-  o.halving_max_depth = 8; o.energy = 0; o.ckpt_every = 1;
+  o.halving_max_depth = 8; o.energy = argc > 10 ? atoi(argv[10]) : 0; o.ckpt_every = 1;
   long long coll;
   if (!strcmp(which, "be"))
     coll = emu::run_grid(grid, [&] {

@@ -30,6 +30,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle.integrate import IntegratorOptions
 from synth import mechanism_file
 from synth.states import paper_sampler, sample_config
 
@@ -106,7 +107,7 @@ def test_block_lu_and_solves_match_lapack(generator, tmp_path_factory, name, lus
         assert np.abs(mu - mr).max() <= bound * np.abs(mr).max()
 
 
-def _integrate(generator, tmp_path_factory, name, which, cfg, nc, dt, n_steps, ld_pad=3, grid=2, lus=0):
+def _integrate(generator, tmp_path_factory, name, which, cfg, nc, dt, n_steps, ld_pad=3, grid=2, lus=0, energy=0):
     exe, d, om = _driver(generator, tmp_path_factory, name)
     T, p, Y = sample_config(cfg, om.ns, nc)
     if any(rx.kind == "plog" for rx in om.reactions):
@@ -119,7 +120,7 @@ def _integrate(generator, tmp_path_factory, name, which, cfg, nc, dt, n_steps, l
     with open(fin, "wb") as f:
         f.write(ys.astype("<f8").tobytes())
         f.write(np.asarray(om.lnA_default, "<f8").tobytes())
-    _run([exe, which, str(nc), str(ld), repr(dt), str(n_steps), fin, fout, str(grid), str(lus)])
+    _run([exe, which, str(nc), str(ld), repr(dt), str(n_steps), fin, fout, str(grid), str(lus), str(energy)])
     raw = open(fout, "rb").read()
     k = 8 * om.n * ld
     y = np.frombuffer(raw[:k], "<f8").reshape(om.n, ld)[:, :nc].T
@@ -160,7 +161,35 @@ def test_block_rosenbrock_matches_oracle(generator, tmp_path_factory, name, lus)
     assert integrated_state_error(om, y, ref["y"]).max() <= 1e-8
 
 
-def test_block_api_kernels_150_species(generator, tmp_path_factory):
+@pytest.mark.parametrize("name,lus", [("ch4like_53_325", 0), ("mix_30_90", 1)])
+def test_block_reactor_backward_euler_matches_oracle(generator, tmp_path_factory, name, lus):
+    """Constant-pressure reactor form (energy 2): the dilatation terms of the sources and of every
+    Jacobian the Newton iterations factor."""
+    om, y0, y, st, cnt = _integrate(generator, tmp_path_factory, name, "be", "be_small", 3, 2e-8, 2, lus=lus,
+                                    energy=oracle.CONST_P_REACTOR)
+    ref = oracle.integrate_be(om, y0, 2e-8, 2, opt=IntegratorOptions(energy=oracle.CONST_P_REACTOR))
+    np.testing.assert_array_equal(st, ref["status"])
+    np.testing.assert_array_equal(cnt[0], ref["steps"])
+    assert int(cnt[2].sum()) == int(ref["newton"].sum())
+    assert integrated_state_error(om, y, ref["y"]).max() <= 1e-8
+    # the reactor form changes the density, and the held-density run differs from it
+    held = oracle.integrate_be(om, y0, 2e-8, 2)
+    assert integrated_state_error(om, y, held["y"]).max() > 1e-6
+
+
+@pytest.mark.parametrize("name,lus", [("ch4like_53_325", 0), ("ch4like_53_325", 1)])
+def test_block_reactor_rosenbrock_matches_oracle(generator, tmp_path_factory, name, lus):
+    om, y0, y, st, cnt = _integrate(generator, tmp_path_factory, name, "ros2", "ros2_methane", 3, 1e-9, 0, lus=lus,
+                                    energy=oracle.CONST_P_REACTOR)
+    ref = oracle.integrate_ros2(om, y0, 1e-9, opt=IntegratorOptions(energy=oracle.CONST_P_REACTOR))
+    np.testing.assert_array_equal(st, ref["status"])
+    np.testing.assert_array_equal(cnt[0], ref["accepted"])
+    np.testing.assert_array_equal(cnt[1], ref["rejected"])
+    assert integrated_state_error(om, y, ref["y"]).max() <= 1e-8
+
+
+@pytest.mark.parametrize("energy", [0, 2])
+def test_block_api_kernels_150_species(generator, tmp_path_factory, energy):
     exe, d, om = _driver(generator, tmp_path_factory, "large_150_1000")
     nc, ld = 3, 5
     T, p, Y = paper_sampler(om.ns, nc, 21)
@@ -171,14 +200,14 @@ def test_block_api_kernels_150_species(generator, tmp_path_factory):
     with open(fin, "wb") as f:
         f.write(ys.astype("<f8").tobytes())
         f.write(np.asarray(om.lnA_default, "<f8").tobytes())
-    _run([exe, "jac", str(nc), str(ld), fin, fout])
+    _run([exe, "jac", str(nc), str(ld), fin, fout, str(energy)])
     raw = np.frombuffer(open(fout, "rb").read(), "<f8")
     S = raw[:om.n * ld].reshape(om.n, ld)[:, :nc].T
     J = raw[om.n * ld:].reshape(nc, om.n, om.n)
-    Sref = oracle.source_terms(om, y)
-    den = np.abs(Sref) + oracle.source_sum_scale(om, y, None, 0)
+    Sref = oracle.source_terms(om, y, None, energy)
+    den = np.abs(Sref) + oracle.source_sum_scale(om, y, None, energy)
     assert (np.abs(S - Sref) / np.where(den > 0, den, 1.0)).max() <= 1e-12
-    Jref, M = oracle.jacobian(om, y, None, 0, magnitude=True)
+    Jref, M = oracle.jacobian(om, y, None, energy, magnitude=True)
     den = np.abs(Jref) + M
     assert (np.abs(J - Jref) / np.where(den > 0, den, 1.0)).max() <= 1e-12
 

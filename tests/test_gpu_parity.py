@@ -67,7 +67,7 @@ def test_thermo(mechs):
     assert np.all(np.abs(g - rg) <= 1e-12 * (np.abs(rg) + np.abs(rs) * T[:, None] + scale))
 
 
-@pytest.mark.parametrize("energy", [0, 1])
+@pytest.mark.parametrize("energy", [0, 1, 2])
 def test_source_terms_and_jacobian(mechs, energy):
     gm, om = mechs
     nc, ld = 200 if om.ns < 20 else 70, 256

@@ -1,0 +1,138 @@
+"""GPU parity of the constant-pressure reactor form (energy CHEM_CONST_P_REACTOR) against the oracle.
+
+* the block form's backward Euler and Rosenbrock (n > 24, both LU strategies where they exist):
+  states within 1e-8 relative, equal step counts, the bar of the other integrator tests;
+* the block-form source-term and Jacobian kernels of the 150-species mechanism: relative 1e-12 of
+  the magnitude of the terms each value sums (the API kernels of the smaller mechanisms are covered
+  by the energy parametrisation of the parity suite);
+* the host refuses the reactor form where the integrator solves the reduced system (n <= 24) and
+  for adjoint tapes, before any kernel runs.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.integrate import IntegratorOptions
+from synth.states import paper_sampler, sample_config
+
+from _gpu import dev_soa, empty, gpu_mechanism, host_aos, integrated_state_error
+
+pytestmark = pytest.mark.gpu
+
+REACTOR = 2
+_ROS2_REF = {}   # oracle runs shared by the two LU strategies
+
+
+@pytest.fixture(scope="module", params=["mix_30_90", "ch4like_53_325"])
+def block_mech(request):
+    print(f"[gpu] loading {request.param}", flush=True)
+    return gpu_mechanism(request.param)
+
+
+def _integrate_gpu(gm, y0, opts, ld):
+    import torch
+    nc = y0.shape[0]
+    y = dev_soa(y0, ld)
+    status = torch.full((ld,), -7, dtype=torch.int32, device="cuda")
+    counters = torch.zeros((3, ld), dtype=torch.int32, device="cuda")
+    gm.chem_integrate(nc, ld, y, None, opts, None, status, counters)
+    torch.cuda.synchronize()
+    return host_aos(y, nc), status.cpu().numpy()[:nc], counters.cpu().numpy()[:, :nc]
+
+
+@pytest.mark.parametrize("lus", [0, 1])
+def test_reactor_backward_euler(block_mech, lus):
+    from paper_2510_10005_amd import CHEM_BE, default_options
+    gm, om = block_mech
+    nc = 40
+    T, p, Y = sample_config("be_small", om.ns, nc)
+    y0 = oracle.state_from_TPY(om, T, p, Y)
+    ref = oracle.integrate_be(om, y0, 6e-8, 6, opt=IntegratorOptions(energy=REACTOR))
+    gm.chem_set_lu_strategy(CHEM_BE, lus)
+    try:
+        print(f"[gpu] reactor BE n={om.n} lus={lus}", flush=True)
+        got, st, cnt = _integrate_gpu(gm, y0, default_options(method=CHEM_BE, dt=6e-8, n_steps=6, energy=REACTOR),
+                                      nc + 5)
+    finally:
+        gm.chem_set_lu_strategy(CHEM_BE, 0)
+    np.testing.assert_array_equal(st, ref["status"])
+    np.testing.assert_array_equal(cnt[0], ref["steps"])
+    err = integrated_state_error(om, got, ref["y"])
+    print(f"[gpu] reactor BE max rel err {err.max():.2e}; newton gpu {cnt[2].sum()} oracle {ref['newton'].sum()}",
+          flush=True)
+    assert err.max() <= 1e-8
+    # the density-holding form gives another answer (the dilatation terms are not negligible here)
+    held = oracle.integrate_be(om, y0, 6e-8, 6)
+    assert integrated_state_error(om, got, held["y"]).max() > 1e-6
+
+
+@pytest.mark.parametrize("lus", [0, 1])
+def test_reactor_rosenbrock(block_mech, lus):
+    from paper_2510_10005_amd import CHEM_ROS2, default_options
+    gm, om = block_mech
+    nc, dt = 16, 3e-9
+    T, p, Y = sample_config("ros2_methane", om.ns, nc)
+    y0 = oracle.state_from_TPY(om, T, p, Y)
+    if om.n not in _ROS2_REF:
+        _ROS2_REF[om.n] = oracle.integrate_ros2(om, y0, dt, opt=IntegratorOptions(energy=REACTOR))
+    ref = _ROS2_REF[om.n]
+    gm.chem_set_lu_strategy(CHEM_ROS2, lus)
+    try:
+        print(f"[gpu] reactor ROS2 n={om.n} lus={lus}", flush=True)
+        got, st, cnt = _integrate_gpu(gm, y0, default_options(method=CHEM_ROS2, dt=dt, energy=REACTOR), nc + 3)
+    finally:
+        gm.chem_set_lu_strategy(CHEM_ROS2, 0)
+    np.testing.assert_array_equal(st, ref["status"])
+    np.testing.assert_array_equal(cnt[0], ref["accepted"])
+    np.testing.assert_array_equal(cnt[1], ref["rejected"])
+    err = integrated_state_error(om, got, ref["y"])
+    print(f"[gpu] reactor ROS2 max rel err {err.max():.2e}; accepted {cnt[0].sum()}", flush=True)
+    assert err.max() <= 1e-8
+
+
+def test_reactor_api_kernels_150_species():
+    import torch
+    gm, om = gpu_mechanism("large_150_1000")
+    nc, ld = 37, 40
+    T, p, Y = paper_sampler(om.ns, nc, 23)
+    y = oracle.state_from_TPY(om, T, p, Y)
+    yd = dev_soa(y, ld)
+    lnA = om.lnA_default + np.random.default_rng(6).uniform(-0.5, 0.5, om.nr)
+    lnA_d = torch.from_numpy(lnA).cuda()
+    print("[gpu] reactor API kernels, 150 species", flush=True)
+    S = empty(om.n, ld)
+    gm.chem_source_terms(nc, ld, yd, lnA_d, REACTOR, S)
+    Sref = oracle.source_terms(om, y, lnA, REACTOR)
+    den = np.abs(Sref) + oracle.source_sum_scale(om, y, lnA, REACTOR)
+    err = np.abs(host_aos(S, nc) - Sref) / np.where(den > 0, den, 1.0)
+    print(f"[gpu] source max scaled err {err.max():.2e}", flush=True)
+    assert np.all(err <= 1e-12)
+    Jd = empty(om.n * om.n, ld)
+    gm.chem_jacobian(nc, ld, yd, lnA_d, REACTOR, Jd)
+    J = host_aos(Jd, nc).reshape(nc, om.n, om.n)
+    Jref, M = oracle.jacobian(om, y, lnA, REACTOR, magnitude=True)
+    err = np.abs(J - Jref) / np.where(np.abs(Jref) + M > 0, np.abs(Jref) + M, 1.0)
+    print(f"[gpu] jacobian max scaled err {err.max():.2e}", flush=True)
+    assert np.all(err <= 1e-12)
+
+
+def test_reactor_refusals():
+    import torch
+    from paper_2510_10005_amd import CHEM_BE, CHEM_ROS2, CHEM_SDIRK2, Tape, default_options
+    from paper_2510_10005_amd._binding import ChemError
+    small, om_s = gpu_mechanism("h2like_10_27")
+    y = torch.zeros((om_s.n, 8), dtype=torch.float64, device="cuda")
+    st = torch.zeros(8, dtype=torch.int32, device="cuda")
+    for method in (CHEM_BE, CHEM_ROS2, CHEM_SDIRK2):
+        with pytest.raises(ChemError, match="reactor"):
+            small.chem_integrate(8, 8, y, None, default_options(method=method, dt=1e-8, n_steps=1, energy=REACTOR),
+                                 None, st, None)
+    big, om_b = gpu_mechanism("mix_30_90")
+    yb = torch.zeros((om_b.n, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(ChemError, match="tape"):
+        big.chem_integrate(8, 8, yb, None, default_options(method=CHEM_BE, dt=1e-8, n_steps=1, energy=REACTOR),
+                           Tape(big, 8, 1), st, None)
+    with pytest.raises(ChemError, match="energy"):
+        big.chem_integrate(8, 8, yb, None, default_options(method=CHEM_BE, dt=1e-8, n_steps=1, energy=3), None, st,
+                           None)
