@@ -180,7 +180,9 @@ def main():
                                                           loss_weights, cfg)
 
     if not args.skip_large:
-        extras["ch4like_53_325"] = large_mechanism_legs(torch, np, dev, args)
+        legs = large_mechanism_legs(torch, np, dev, args)
+        extras["large_150_1000"] = legs.pop("large_150_1000")
+        extras["ch4like_53_325"] = legs
 
     cpu = None
     if not args.skip_cpu:

@@ -177,7 +177,7 @@ def test_block_reactor_backward_euler_matches_oracle(generator, tmp_path_factory
     assert integrated_state_error(om, y, held["y"]).max() > 1e-6
 
 
-@pytest.mark.parametrize("name,lus", [("ch4like_53_325", 0), ("ch4like_53_325", 1)])
+@pytest.mark.parametrize("name,lus", [("ch4like_53_325", 1)])
 def test_block_reactor_rosenbrock_matches_oracle(generator, tmp_path_factory, name, lus):
     om, y0, y, st, cnt = _integrate(generator, tmp_path_factory, name, "ros2", "ros2_methane", 3, 1e-9, 0, lus=lus,
                                     energy=oracle.CONST_P_REACTOR)
