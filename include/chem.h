@@ -109,10 +109,12 @@ enum { CHEM_FLAG_CHECK_CELLS = 1 };  /* synchronise and return CHEM_ECELLS if a 
  *           CHEM_CONST_V: omega_T = -sum U_i omega_i / sum C_i Cv_i (Section 3)
  *           CHEM_CONST_P_REACTOR: the constant-pressure reactor with its density change (the
  *           omega_T of CHEM_CONST_P, species sources omega_i - C_i g; see chem_source_terms).
- *           Backward Euler and Rosenbrock of mechanisms with n > 24 only, without tapes
- *           (CHEM_EUNSUPPORTED otherwise: the other integrators solve the reduced system of the
- *           species that take part in reactions, which holds the inert species fixed, while the
- *           reactor's expansion changes every concentration).
+ *           Every method and form, without tapes (CHEM_EUNSUPPORTED).  Its expansion changes
+ *           every concentration, so for n <= 24 the integrators run a second build of the
+ *           mechanism whose solved system holds every species (the regular one holds the species
+ *           that take part in no reaction fixed); it is generated, compiled (or taken from the
+ *           kernel cache, where chem_precompile puts it) and loaded on the first such call.
+ *           chem_integrate_noalloc refuses the mode until that has happened.
  *  form     CHEM_PERSISTENT: one persistent kernel, cells pulled from a work queue lane by lane.
  *           CHEM_PLAIN: one kernel launch per substep (BE: per full step) over all cells.
  *  Newton convergence: max_i |delta_i| / sc_i <= 1 with sc_T = newton_rtol T + newton_atol_T and,

@@ -48,14 +48,17 @@ def build_library(verbose: bool = True) -> str:
 
 
 def precompile(mech_paths, cache_dir: str = KERNEL_CACHE, verbose: bool = True):
-    """Generate and hipRTC-compile (gfx950) the kernels of each mechanism file into cache_dir."""
+    """Generate and hipRTC-compile (gfx950) the kernels of each mechanism file into cache_dir, several
+    mechanisms at a time (each compile is one host thread; the C call releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     from . import _binding
-    out = []
-    for p in mech_paths:
-        path = _binding.precompile(p, cache_dir)
-        if verbose:
+    workers = max(1, min(len(mech_paths), len(os.sched_getaffinity(0)), 16))
+    with ThreadPoolExecutor(workers) as pool:
+        out = list(pool.map(lambda p: _binding.precompile(p, cache_dir), mech_paths))
+    if verbose:
+        for p, path in zip(mech_paths, out):
             print(f"precompiled {os.path.basename(p)} -> {path}", flush=True)
-        out.append(path)
     return out
 
 

@@ -204,20 +204,25 @@ void build_one(const std::string& src, const std::string& arch, const std::strin
 }
 
 // generate + compile (or fetch from the cache) the code objects of a mechanism: one entry for a
-// register-resident mechanism, kGroups entries otherwise
+// register-resident mechanism, kGroups entries otherwise.  full_system (register-resident
+// mechanisms): the build whose integrators solve for every species, groups 1 (Rosenbrock) and 2
+// (backward Euler, SDIRK, YASS) only.
 chem_err build_code_objects(const chem::Mechanism& m, const std::string& arch, const std::string& cache_dir,
-                            std::vector<CodeObject>& objs) {
-  const std::string src = chem::generate_source(m, kDenseLimit);
+                            std::vector<CodeObject>& objs, bool full_system = false) {
+  const std::string src = chem::generate_source(m, kDenseLimit, full_system);
   const bool split = m.n() > kDenseLimit;
-  objs.assign(split ? kGroups : 1, CodeObject{});
-  if (!split) {
-    build_one(src, arch, cache_dir, -1, objs[0]);
-  } else {
-    std::vector<std::thread> th;
-    for (int g = 0; g < kGroups; ++g)
-      th.emplace_back([&, g] { build_one(src, arch, cache_dir, g, objs[g]); });
-    for (auto& t : th) t.join();
-  }
+  std::vector<int> groups;
+  if (full_system)
+    groups = {1, 2};
+  else if (split)
+    for (int g = 0; g < kGroups; ++g) groups.push_back(g);
+  else
+    groups = {-1};
+  objs.assign(groups.size(), CodeObject{});
+  std::vector<std::thread> th;
+  for (size_t i = 0; i < groups.size(); ++i)
+    th.emplace_back([&, i] { build_one(src, arch, cache_dir, groups[i], objs[i]); });
+  for (auto& t : th) t.join();
   for (auto& o : objs)
     if (o.err) return fail(o.err, o.msg);
   return CHEM_OK;
@@ -280,6 +285,12 @@ struct chem_mech {
   std::string arch;
   std::vector<hipModule_t> modules;
   hipFunction_t fn[K_COUNT] = {};
+  // full-system build of a register-resident mechanism (integrators in the reactor energy mode),
+  // loaded on first use (under mu)
+  std::vector<hipModule_t> modules_full;
+  hipFunction_t fn_full[K_COUNT] = {};
+  bool full_loaded = false;
+  std::string cache_dir;
   bool dense = true;
   bool wave = false;      // n > 24: table-driven evaluation; integrators one cell per 256-thread workgroup
   bool wave_api = false;  // 24 < n <= 64: Jacobian API kernel one cell per 64-lane wavefront
@@ -301,15 +312,32 @@ struct chem_mech {
     if (fence) (void)hipEventDestroy(fence);
     if (running_host) (void)hipHostFree(running_host);
     for (hipModule_t md : modules) (void)hipModuleUnload(md);
+    for (hipModule_t md : modules_full) (void)hipModuleUnload(md);
   }
 };
 
 namespace {
 
+// The build the calling thread's current integration uses: the full-system one (reactor energy
+// mode of a register-resident mechanism) or the regular one.  Per thread, so that calls on other
+// threads are not affected; set by FullSystemScope.
+thread_local bool t_full_system = false;
+
+struct FullSystemScope {
+  bool prev;
+  explicit FullSystemScope(bool on) : prev(t_full_system) { t_full_system = on; }
+  ~FullSystemScope() { t_full_system = prev; }
+};
+
+hipFunction_t kernel_fn(const chem_mech* M, KernelId k) { return t_full_system ? M->fn_full[k] : M->fn[k]; }
+
+// size of the system the integrators solve: T and the reacting species, or every component
+int solved_size(const chem_mech* M) { return t_full_system ? M->m.n() : M->n_active; }
+
 chem_err launch(const chem_mech* M, KernelId k, unsigned grid, unsigned block, hipStream_t s, void** args,
                 unsigned shmem = 0) {
   if (grid == 0) return CHEM_OK;
-  hipError_t e = hipModuleLaunchKernel(M->fn[k], grid, 1, 1, block, 1, 1, shmem, s, args, nullptr);
+  hipError_t e = hipModuleLaunchKernel(kernel_fn(M, k), grid, 1, 1, block, 1, 1, shmem, s, args, nullptr);
   if (e != hipSuccess) return fail(CHEM_EDEVICE, std::string("launch of ") + kKernelNames[k] + ": " + hipGetErrorString(e));
   return CHEM_OK;
 }
@@ -317,7 +345,7 @@ chem_err launch(const chem_mech* M, KernelId k, unsigned grid, unsigned block, h
 chem_err launch2d(const chem_mech* M, KernelId k, unsigned gx, unsigned gy, unsigned block, hipStream_t s,
                   void** args) {
   if (gx == 0 || gy == 0) return CHEM_OK;
-  hipError_t e = hipModuleLaunchKernel(M->fn[k], gx, gy, 1, block, 1, 1, 0, s, args, nullptr);
+  hipError_t e = hipModuleLaunchKernel(kernel_fn(M, k), gx, gy, 1, block, 1, 1, 0, s, args, nullptr);
   if (e != hipSuccess) return fail(CHEM_EDEVICE, std::string("launch of ") + kKernelNames[k] + ": " + hipGetErrorString(e));
   return CHEM_OK;
 }
@@ -396,12 +424,11 @@ DevYassOpts yass_to_dev(const chem_integrator_opts& o) {
 bool known_energy(int e) { return e == CHEM_CONST_P || e == CHEM_CONST_V || e == CHEM_CONST_P_REACTOR; }
 
 // The reactor form changes every concentration (the density follows T and the mole number), so it
-// needs integrators that solve the full system: those of the block form (n > 24), without tapes.
+// needs integrators that solve the full system: the block form's (n > 24) and, for register-resident
+// mechanisms, those of the full-system build.  No tapes (the adjoints have no dilatation terms).
 chem_err check_reactor(const chem_mech* M, const chem_integrator_opts* o, bool tape) {
+  (void)M;
   if (o->energy != CHEM_CONST_P_REACTOR) return CHEM_OK;
-  if (!M->wave || (o->method != CHEM_BE && o->method != CHEM_ROS2))
-    return fail(CHEM_EUNSUPPORTED, "the constant-pressure reactor form integrates with backward Euler or "
-                "Rosenbrock for mechanisms with n > 24");
   if (tape) return fail(CHEM_EUNSUPPORTED, "no adjoint tape for the constant-pressure reactor form");
   return CHEM_OK;
 }
@@ -433,11 +460,32 @@ chem_err validate_opts(const chem_integrator_opts* o) {
   return CHEM_OK;
 }
 
+// the full-system build of a register-resident mechanism (groups 1 and 2: every integrator), once;
+// the kernels of the other groups come from the regular build.  Called under M->mu.
+chem_err load_full_system(chem_mech* M) {
+  if (M->full_loaded) return CHEM_OK;
+  std::vector<CodeObject> objs;
+  if (chem_err e = build_code_objects(M->m, M->arch, M->cache_dir, objs, true)) return e;
+  for (auto& o : objs) {
+    hipModule_t md = nullptr;
+    HIP_TRY(hipModuleLoadData(&md, o.code.data()));
+    M->modules_full.push_back(md);
+  }
+  for (int k = 0; k < K_COUNT; ++k) {
+    const int g = kKernelGroup[k];
+    M->fn_full[k] = M->fn[k];
+    if ((g != 1 && g != 2) || lu_strategy_kernel(k)) continue;
+    HIP_TRY(hipModuleGetFunction(&M->fn_full[k], M->modules_full[g - 1], kKernelNames[k]));
+  }
+  M->full_loaded = true;
+  return CHEM_OK;
+}
+
 // dynamic LDS of a launch: the Rosenbrock kernels park the upper LU factor of each lane
 // (register-resident mechanisms only)
 unsigned shmem_for(const chem_mech* M, KernelId k, int block) {
   if (!M->dense || (k != K_ROS2_PERSISTENT && k != K_ROS2_PERSISTENT_REC && k != K_ROS2_STEP)) return 0;
-  const int na = M->n_active;
+  const int na = solved_size(M);
   return static_cast<unsigned>(na * (na + 1) / 2) * static_cast<unsigned>(block) * sizeof(double);
 }
 
@@ -446,7 +494,7 @@ bool shmem_fits(const chem_mech* M, KernelId k, int block) { return shmem_for(M,
 // blocks per CU the runtime reports for a kernel at this block size (>= 1)
 int occupancy_blocks(const chem_mech* M, KernelId k, int block) {
   int nb = 0;
-  if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, M->fn[k], block, shmem_for(M, k, block)) != hipSuccess ||
+  if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_fn(M, k), block, shmem_for(M, k, block)) != hipSuccess ||
       nb < 1)
     nb = 1;
   return nb;
@@ -528,6 +576,10 @@ chem_err chem_precompile(const char* path, const char* cache_dir, char* path_out
   std::vector<CodeObject> objs;
   e = build_code_objects(m, "gfx950", cache_dir ? cache_dir : default_cache_dir(), objs);
   if (e) return e;
+  if (m.n() <= kDenseLimit) {  // the full-system build too (its paths are not reported)
+    std::vector<CodeObject> full;
+    if ((e = build_code_objects(m, "gfx950", cache_dir ? cache_dir : default_cache_dir(), full, true))) return e;
+  }
   if (path_out && cap) {
     std::string paths;
     for (auto& o : objs) paths += (paths.empty() ? "" : ";") + o.path;
@@ -583,6 +635,7 @@ chem_err chem_load_mechanism(const char* path, const char* cache_dir, chem_mech*
       for (auto& p : M->m.net(j)) act[p.first] = true;
     M->n_active = 1 + static_cast<int>(std::count(act.begin(), act.end(), true));
   }
+  M->cache_dir = cache_dir ? cache_dir : default_cache_dir();
   std::vector<double> lnA(std::max(1, M->m.nr()), 0.0);
   for (int j = 0; j < M->m.nr(); ++j) lnA[j] = M->m.reactions[j].k.lnA;
   if ((e = M->lnA_default.ensure(lnA.size() * sizeof(double)))) return e;
@@ -858,6 +911,17 @@ chem_err integrate_impl(chem_mech* M, int64_t n, int64_t ld, double* y, const do
   }
   if (n == 0) return CHEM_OK;
   std::lock_guard<std::mutex> lock(M->mu);
+  // the reactor mode of a register-resident mechanism runs the full-system build (compiled or
+  // fetched from the cache and loaded on first use; the allocation-free entry point only uses it
+  // once loaded)
+  const bool full = opts->energy == CHEM_CONST_P_REACTOR && M->dense;
+  if (full && !M->full_loaded) {
+    if (fw)
+      return fail(CHEM_EUNSUPPORTED, "the reactor mode of this mechanism needs its full-system build, which "
+                  "chem_integrate_noalloc does not load (run chem_integrate once in that mode first)");
+    if (chem_err e = load_full_system(M)) return e;
+  }
+  FullSystemScope scope(full);
   hipStream_t s = static_cast<hipStream_t>(stream);
   StreamFence fence(M, s);
   if (chem_err e = fence.begin()) return e;
@@ -1188,6 +1252,12 @@ chem_err chem_autotune(chem_mech* M, int64_t n, int64_t ld, const double* y, con
   if (M->wave && opts->method != CHEM_BE && opts->method != CHEM_ROS2)
     return fail(CHEM_EUNSUPPORTED, std::string(method_name(opts->method)) + " is implemented for n <= 24");
   if (n == 0) return CHEM_OK;
+  const bool full = opts->energy == CHEM_CONST_P_REACTOR && M->dense;
+  if (full) {
+    std::lock_guard<std::mutex> lock(M->mu);
+    if (chem_err e = load_full_system(M)) return e;
+  }
+  FullSystemScope scope(full);   // the occupancy queries below see the build the trials run
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int NY = M->m.n();
   DevBuf ycopy, st;

@@ -602,13 +602,16 @@ static void emit_block_jac_tables(std::ostringstream& os, const Mechanism& m, in
   os << "};\n";
 }
 
-std::string generate_source(const Mechanism& m, int dense_limit) {
+std::string generate_source(const Mechanism& m, int dense_limit, bool full_system) {
   std::ostringstream os;
   const int ns = m.ns(), nr = m.nr(), n = m.n();
+  full_system = full_system && n <= dense_limit;
   os << kPrelude;
   os << "// ---------------------------------------------------------------- generated mechanism block\n";
   os << "#define NS " << ns << "\n#define NY " << n << "\n#define NR " << (nr > 0 ? nr : 1) << "\n";
   os << "#define CHEM_DENSE " << (n <= dense_limit ? 1 : 0) << "\n";
+  // full-system build: the integrators solve for every state component (the reactor energy mode)
+  os << "#define CHEM_FULL_SYSTEM " << (full_system ? 1 : 0) << "\n";
   os << "#if CHEM_DENSE\n#define CHEM_MUNROLL _Pragma(\"unroll\")\n#define CHEM_EVAL_INLINE __forceinline__\n"
         "#else\n#define CHEM_MUNROLL _Pragma(\"unroll 1\")\n#define CHEM_EVAL_INLINE __noinline__\n#endif\n";
   os << "#define CHEM_R 8314.462618\n";
@@ -710,6 +713,7 @@ std::string generate_source(const Mechanism& m, int dense_limit) {
   std::vector<bool> sp_active(ns, false);
   for (int j = 0; j < nr; ++j)
     for (auto& p : m.net(j)) sp_active[p.first] = true;
+  if (full_system) std::fill(sp_active.begin(), sp_active.end(), true);
   red[0] = 0;
   act.push_back(0);
   for (int i = 0; i < ns; ++i)

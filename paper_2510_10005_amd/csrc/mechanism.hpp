@@ -63,6 +63,7 @@ Mechanism parse_mechanism(const std::string& json_text);
 
 // Generated HIP source for the mechanism (everything the kernels need, constants folded).
 // dense_limit: state sizes up to this use register-resident Jacobian/LU storage.
-std::string generate_source(const Mechanism& m, int dense_limit);
+// full_system (register-resident mechanisms only): every species in the integrators' solved system
+std::string generate_source(const Mechanism& m, int dense_limit, bool full_system = false);
 
 }  // namespace chem

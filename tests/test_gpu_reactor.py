@@ -5,8 +5,12 @@
 * the block-form source-term and Jacobian kernels of the 150-species mechanism: relative 1e-12 of
   the magnitude of the terms each value sums (the API kernels of the smaller mechanisms are covered
   by the energy parametrisation of the parity suite);
-* the host refuses the reactor form where the integrator solves the reduced system (n <= 24) and
-  for adjoint tapes, before any kernel runs.
+* the register-resident form (n <= 24) runs the reactor mode with its full-system build (every
+  species in the solved system): backward Euler (persistent and plain), Rosenbrock (persistent and
+  plain), SDIRK-2, SDIRK-4 and YASS with LU against the oracle on the same bar, and the regular
+  build keeps running the other modes in the same process;
+* the host refuses the reactor form for adjoint tapes and unknown energy modes before any kernel
+  runs.
 """
 
 import numpy as np
@@ -91,6 +95,74 @@ def test_reactor_rosenbrock(block_mech, lus):
     assert err.max() <= 1e-8
 
 
+def _register_ref(om, y0, method, dt, n_steps):
+    opt = IntegratorOptions(energy=REACTOR)
+    if method == "be":
+        return oracle.integrate_be(om, y0, dt, n_steps, opt=opt)
+    if method == "ros2":
+        return oracle.integrate_ros2(om, y0, dt, opt=opt)
+    if method == "sdirk2":
+        return oracle.integrate_sdirk2(om, y0, dt, n_steps, opt=opt)
+    if method == "sdirk4":
+        return oracle.integrate_sdirk4(om, y0, dt, n_steps, opt=opt)
+    return oracle.integrate_yass(om, y0, dt, n_steps, opt=opt)
+
+
+_REGISTER_REF = {}   # oracle runs shared by the persistent and plain forms
+REGISTER_CASES = {
+    # name: (method, form, dt, n_steps)
+    "be": ("be", 0, 2e-6, 4),
+    "be_plain": ("be", 1, 2e-6, 4),
+    "ros2": ("ros2", 0, 2e-7, 0),
+    "ros2_plain": ("ros2", 1, 2e-7, 0),
+    "sdirk2": ("sdirk2", 0, 2e-6, 4),
+    "sdirk4": ("sdirk4", 0, 2e-6, 4),
+    "yass_lu": ("yass", 0, 2e-6, 2),
+}
+
+
+@pytest.mark.parametrize("name", ["tiny_8_14", "h2like_10_27"])
+@pytest.mark.parametrize("case", list(REGISTER_CASES))
+def test_reactor_register_form(name, case):
+    import paper_2510_10005_amd as P
+    from paper_2510_10005_amd import default_options
+    gm, om = gpu_mechanism(name)
+    method, form, dt, n_steps = REGISTER_CASES[case]
+    nc = 130
+    T, p, Y = sample_config("be_small", om.ns, nc)
+    y0 = oracle.state_from_TPY(om, T, p, Y)
+    key = (name, method, dt, n_steps)
+    if key not in _REGISTER_REF:
+        with np.errstate(all="ignore"):
+            _REGISTER_REF[key] = _register_ref(om, y0, method, dt, n_steps)
+    ref = _REGISTER_REF[key]
+    code = {"be": P.CHEM_BE, "ros2": P.CHEM_ROS2, "sdirk2": P.CHEM_SDIRK2, "sdirk4": P.CHEM_SDIRK4,
+            "yass": P.CHEM_YASS}[method]
+    print(f"[gpu] reactor {name} {case}", flush=True)
+    got, st, cnt = _integrate_gpu(gm, y0, default_options(method=code, dt=dt, n_steps=n_steps, form=form,
+                                                          energy=REACTOR), nc + 3)
+    np.testing.assert_array_equal(st, ref["status"])
+    if "steps" in ref:
+        np.testing.assert_array_equal(cnt[0], ref["steps"])
+    else:
+        np.testing.assert_array_equal(cnt[0], ref["accepted"])
+        np.testing.assert_array_equal(cnt[1], ref["rejected"])
+    ok = ref["status"] == 0
+    err = integrated_state_error(om, got[ok], ref["y"][ok])
+    print(f"[gpu] reactor {name} {case}: {ok.sum()} cells, max rel err {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-8
+    # the inert collider's concentration changes with the density (the reduced system holds it)
+    inert = 1 + np.nonzero(om.inert)[0]
+    assert np.abs(got[ok][:, inert] / y0[ok][:, inert] - 1.0).max() > 1e-6
+    # the regular build still serves the density-holding mode in the same process
+    if case == "be":
+        held = oracle.integrate_be(om, y0, dt, n_steps)
+        g0, s0, c0 = _integrate_gpu(gm, y0, default_options(method=code, dt=dt, n_steps=n_steps), nc + 3)
+        np.testing.assert_array_equal(s0, held["status"])
+        assert integrated_state_error(om, g0[s0 == 0], held["y"][s0 == 0]).max() <= 1e-8
+        assert np.array_equal(g0[:, inert], y0[:, inert])
+
+
 def test_reactor_api_kernels_150_species():
     import torch
     gm, om = gpu_mechanism("large_150_1000")
@@ -119,15 +191,17 @@ def test_reactor_api_kernels_150_species():
 
 def test_reactor_refusals():
     import torch
-    from paper_2510_10005_amd import CHEM_BE, CHEM_ROS2, CHEM_SDIRK2, Tape, default_options
+    from paper_2510_10005_amd import CHEM_BE, CHEM_ROS2, Tape, default_options
     from paper_2510_10005_amd._binding import ChemError
     small, om_s = gpu_mechanism("h2like_10_27")
     y = torch.zeros((om_s.n, 8), dtype=torch.float64, device="cuda")
     st = torch.zeros(8, dtype=torch.int32, device="cuda")
-    for method in (CHEM_BE, CHEM_ROS2, CHEM_SDIRK2):
-        with pytest.raises(ChemError, match="reactor"):
-            small.chem_integrate(8, 8, y, None, default_options(method=method, dt=1e-8, n_steps=1, energy=REACTOR),
-                                 None, st, None)
+    with pytest.raises(ChemError, match="tape"):
+        small.chem_integrate(8, 8, y, None, default_options(method=CHEM_BE, dt=1e-8, n_steps=1, energy=REACTOR),
+                             Tape(small, 8, 1), st, None)
+    with pytest.raises(ChemError, match="tape"):
+        small.chem_integrate(8, 8, y, None, default_options(method=CHEM_ROS2, dt=1e-8, energy=REACTOR),
+                             Tape(small, 8, 1, method=CHEM_ROS2, max_steps=16), st, None)
     big, om_b = gpu_mechanism("mix_30_90")
     yb = torch.zeros((om_b.n, 8), dtype=torch.float64, device="cuda")
     with pytest.raises(ChemError, match="tape"):
