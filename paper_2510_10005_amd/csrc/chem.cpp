@@ -1040,7 +1040,10 @@ chem_err integrate_impl(chem_mech* M, int64_t n, int64_t ld, double* y, const do
       if ((e = launch(M, k, grid, block, s, args))) return e;
     }
   } else {
-    const int block = M->wave ? 64 : (M->launch_block[method][CHEM_PLAIN] ? M->launch_block[method][CHEM_PLAIN] : 64);
+    int block = M->wave ? 64 : (M->launch_block[method][CHEM_PLAIN] ? M->launch_block[method][CHEM_PLAIN] : 64);
+    // the Rosenbrock step parks U in LDS, which grows with the solved system (the full-system build
+    // of the reactor mode solves more components than the launch shape may have been set for)
+    while (method == CHEM_ROS2 && block > 64 && !shmem_fits(M, K_ROS2_STEP, block)) block /= 2;
     const unsigned grid = M->wave ? static_cast<unsigned>(n) : blocks_for(n, block);
     int64_t slots = n;
     double* ws = nullptr;

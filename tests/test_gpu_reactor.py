@@ -163,6 +163,31 @@ def test_reactor_register_form(name, case):
         assert np.array_equal(g0[:, inert], y0[:, inert])
 
 
+def test_reactor_rosenbrock_launch_shape_larger_system():
+    """The 12-species mechanism's reduced system (12 components) parks its U factor in 159,744 B of
+    LDS at 256 threads per block; the full-system build (13) would need 186,368 B.  A launch shape
+    set for the regular build is narrowed for the reactor mode instead of failing, in both forms."""
+    import paper_2510_10005_amd as P
+    from paper_2510_10005_amd import default_options
+    gm, om = gpu_mechanism("sri_12_30")
+    nc = 96
+    T, p, Y = sample_config("be_small", om.ns, nc)
+    y0 = oracle.state_from_TPY(om, T, p, Y)
+    with np.errstate(all="ignore"):
+        ref = oracle.integrate_ros2(om, y0, 1e-7, opt=IntegratorOptions(energy=REACTOR))
+    for form in (P.CHEM_PERSISTENT, P.CHEM_PLAIN):
+        gm.chem_set_launch(P.CHEM_ROS2, form, 256, 0)
+        try:
+            print(f"[gpu] reactor ROS2 12 species, form {form}, block 256 requested", flush=True)
+            got, st, cnt = _integrate_gpu(gm, y0, default_options(method=P.CHEM_ROS2, dt=1e-7, form=form,
+                                                                  energy=REACTOR), nc + 3)
+        finally:
+            gm.chem_set_launch(P.CHEM_ROS2, form, 0, 0)
+        np.testing.assert_array_equal(st, ref["status"])
+        np.testing.assert_array_equal(cnt[0], ref["accepted"])
+        assert integrated_state_error(om, got, ref["y"]).max() <= 1e-8
+
+
 def test_reactor_api_kernels_150_species():
     import torch
     gm, om = gpu_mechanism("large_150_1000")
