@@ -151,7 +151,7 @@ def test_block_backward_euler_recorded_geometry(generator, tmp_path_factory):
     assert integrated_state_error(om, y, ref["y"]).max() <= 1e-8
 
 
-@pytest.mark.parametrize("name,lus", [("ch4like_53_325", 0), ("mix_30_90", 0), ("mix_30_90", 1)])
+@pytest.mark.parametrize("name,lus", [("ch4like_53_325", 0), ("mix_30_90", 1)])
 def test_block_rosenbrock_matches_oracle(generator, tmp_path_factory, name, lus):
     om, y0, y, st, cnt = _integrate(generator, tmp_path_factory, name, "ros2", "ros2_methane", 3, 1e-9, 0, lus=lus)
     ref = oracle.integrate_ros2(om, y0, 1e-9)
