@@ -5,7 +5,8 @@ allocation once its buffers exist, so it can be captured.  Each replay re-integr
 initial states; every replay must reproduce the eager call bit for bit (cells are independent and
 each lane runs the same instruction sequence), with eager work and synchronisations between the
 replays.  Both the register form (10 species) and the block form (53 species, one cell per
-workgroup, probe/resume schedule) are captured.
+workgroup, probe/resume schedule) are captured, and the constant-pressure reactor mode (energy 2:
+the register form's full-system build) as well.
 """
 
 import numpy as np
@@ -19,9 +20,10 @@ from _gpu import gpu_mechanism
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("mech,method,n", [("h2like_10_27", "ros2", 6000), ("h2like_10_27", "be", 6000),
-                                           ("ch4like_53_325", "ros2", 600), ("ch4like_53_325", "be", 600)])
-def test_graph_replay_matches_eager(mech, method, n):
+@pytest.mark.parametrize("mech,method,n,energy", [("h2like_10_27", "ros2", 6000, 0), ("h2like_10_27", "be", 6000, 0),
+                                                  ("ch4like_53_325", "ros2", 600, 0), ("ch4like_53_325", "be", 600, 0),
+                                                  ("h2like_10_27", "ros2", 6000, 2), ("ch4like_53_325", "be", 600, 2)])
+def test_graph_replay_matches_eager(mech, method, n, energy):
     from paper_2510_10005_amd import CHEM_BE, CHEM_PERSISTENT, CHEM_ROS2, default_options
     gm, om = gpu_mechanism(mech)
     cfg = STATE_CONFIGS["ros2_1m"]
@@ -30,9 +32,9 @@ def test_graph_replay_matches_eager(mech, method, n):
     y0 = torch.empty((om.n, n), dtype=torch.float64, device="cuda")
     gm.chem_state_from_TPY(n, n, d(T), d(p), d(Y.T), y0)
     if method == "ros2":
-        opts = default_options(method=CHEM_ROS2, dt=1e-6, n_steps=0, form=CHEM_PERSISTENT)
+        opts = default_options(method=CHEM_ROS2, dt=1e-6, n_steps=0, form=CHEM_PERSISTENT, energy=energy)
     else:
-        opts = default_options(method=CHEM_BE, dt=1e-6, n_steps=20, form=CHEM_PERSISTENT)
+        opts = default_options(method=CHEM_BE, dt=1e-6, n_steps=20, form=CHEM_PERSISTENT, energy=energy)
     y = torch.empty_like(y0)
     st = torch.empty(n, dtype=torch.int32, device="cuda")
     cnt = torch.zeros((3, n), dtype=torch.int32, device="cuda")

@@ -188,6 +188,30 @@ def test_reactor_rosenbrock_launch_shape_larger_system():
         assert integrated_state_error(om, got, ref["y"]).max() <= 1e-8
 
 
+def test_reactor_autotune_register_form():
+    """chem_autotune in the reactor mode times the full-system build's kernels (its occupancy and
+    LDS limits) and leaves a launch shape that integrates correctly."""
+    import paper_2510_10005_amd as P
+    from paper_2510_10005_amd import default_options
+    gm, om = gpu_mechanism("mid_14_40")
+    nc = 2000
+    T, p, Y = sample_config("be_small", om.ns, nc)
+    y0 = oracle.state_from_TPY(om, T, p, Y)
+    opts = default_options(method=P.CHEM_ROS2, dt=1e-7, energy=REACTOR)
+    gm.chem_autotune(nc, nc, dev_soa(y0, nc), None, opts)
+    print(f"[gpu] reactor autotuned launch {gm.chem_get_launch(P.CHEM_ROS2, P.CHEM_PERSISTENT)}", flush=True)
+    idx = np.arange(0, nc, 16)
+    with np.errstate(all="ignore"):
+        ref = oracle.integrate_ros2(om, y0[idx], 1e-7, opt=IntegratorOptions(energy=REACTOR))
+    try:
+        got, st, cnt = _integrate_gpu(gm, y0, opts, nc)
+    finally:
+        gm.chem_set_launch(P.CHEM_ROS2, P.CHEM_PERSISTENT, 0, 0)
+    np.testing.assert_array_equal(st[idx], ref["status"])
+    np.testing.assert_array_equal(cnt[0][idx], ref["accepted"])
+    assert integrated_state_error(om, got[idx], ref["y"]).max() <= 1e-8
+
+
 def test_reactor_api_kernels_150_species():
     import torch
     gm, om = gpu_mechanism("large_150_1000")
