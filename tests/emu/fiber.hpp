@@ -79,10 +79,13 @@ inline int wave_arrive(int line, long long& k) {
   if (me == 0) ++B.collectives;
   return b;
 }
+// A workgroup of fewer than 64 threads is one partial wave: the missing lanes are inactive (they
+// take part in no collective, contribute 0 to a ballot and read as 0 through a shuffle).
 inline void wave_check(long long k, int b, int line) {
   Block& B = *g_blk;
   const int me = B.cur, w0 = me & ~63;
-  for (int l = w0; l < w0 + 64; ++l) {
+  const int w1 = w0 + 64 < B.nthreads ? w0 + 64 : B.nthreads;
+  for (int l = w0; l < w1; ++l) {
     // lanes earlier in the round may already have gone on (or finished) after this collective
     if (B.seq[l] < k + 1) diverged("lane of the wave finished before this collective", l, B.site[b][l], me, line);
     if (B.site[b][l] != line) diverged("lanes of one wave at different collectives", l, B.site[b][l], me, line);
@@ -100,8 +103,9 @@ inline T exchange(T v, int src, int line) {
   B.slot[b][B.cur] = bits;
   yield_next();
   wave_check(k, b, line);
-  T r;
-  std::memcpy(&r, &B.slot[b][(B.cur & ~63) + (src & 63)], sizeof(T));
+  T r{};
+  const int s = (B.cur & ~63) + (src & 63);
+  if (s < B.nthreads) std::memcpy(&r, &B.slot[b][s], sizeof(T));
   return r;
 }
 inline unsigned long long ballot(bool p, int line) {
@@ -113,7 +117,7 @@ inline unsigned long long ballot(bool p, int line) {
   wave_check(k, b, line);
   unsigned long long m = 0;
   const int w0 = B.cur & ~63;
-  for (int l = 0; l < 64; ++l)
+  for (int l = 0; l < 64 && w0 + l < B.nthreads; ++l)
     if (B.slot[b][w0 + l]) m |= 1ull << l;
   return m;
 }
@@ -203,7 +207,7 @@ inline void thread_entry(unsigned lo, unsigned hi) {
   B.done[me] = true;
   // every other lane of the wave must also be finished or finish in this round
   const int w0 = me & ~63;
-  for (int l = w0; l < w0 + 64; ++l)
+  for (int l = w0; l < w0 + 64 && l < B.nthreads; ++l)
     if (!B.done[l] && B.seq[l] != B.seq[me]) diverged("lane finished while another is inside a collective", me, -1, l, -1);
   for (int s = 1; s <= B.nthreads; ++s) {
     const int nx = (me + s) % B.nthreads;
