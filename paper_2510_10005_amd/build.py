@@ -47,15 +47,25 @@ def build_library(verbose: bool = True) -> str:
     return LIB
 
 
+def _precompile_one(job):
+    from . import _binding
+    path, cache_dir = job
+    return _binding.precompile(path, cache_dir)
+
+
 def precompile(mech_paths, cache_dir: str = KERNEL_CACHE, verbose: bool = True):
     """Generate and hipRTC-compile (gfx950) the kernels of each mechanism file into cache_dir, several
-    mechanisms at a time (each compile is one host thread; the C call releases the GIL)."""
-    from concurrent.futures import ThreadPoolExecutor
+    mechanisms at a time in worker processes (hipRTC compiles of one process do not overlap)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
 
-    from . import _binding
     workers = max(1, min(len(mech_paths), len(os.sched_getaffinity(0)), 16))
-    with ThreadPoolExecutor(workers) as pool:
-        out = list(pool.map(lambda p: _binding.precompile(p, cache_dir), mech_paths))
+    jobs = [(p, cache_dir) for p in mech_paths]
+    if workers == 1:
+        out = [_precompile_one(j) for j in jobs]
+    else:
+        with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as pool:
+            out = list(pool.map(_precompile_one, jobs))
     if verbose:
         for p, path in zip(mech_paths, out):
             print(f"precompiled {os.path.basename(p)} -> {path}", flush=True)
