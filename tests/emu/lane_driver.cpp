@@ -6,7 +6,9 @@
 // the fiber emulation (all lanes of a wave at every collective) cannot follow; with one lane per
 // wave every collective is uniform.  One workgroup pulls every cell from the queue.
 // Usage:
-//   lane_driver ros2adj n ld dt K in.bin out.bin
+//   lane_driver ros2adj n ld dt K in.bin out.bin [probe]
+//     probe > 0: the recording run as the library issues it with a probe budget: probe launch (each
+//     cell at most `probe` attempts), bin scan, scatter of the parked cells, resume launch
 //     in.bin: state [NY][ld], ln A [NR], dL/dy_N [NY][ld]
 //     out.bin: final state [NY][ld], status [ld], accepted steps [ld], dL/dy0 [NY][ld], dL/dlnA [NR]
 // The test includes the generated source with two textual changes: the dynamic LDS declaration
@@ -44,10 +46,26 @@ int main(int argc, char** argv) {
   std::vector<double> ck((size_t)(cap / K + 2) * NY * ld, 0.0);
   std::copy(y.begin(), y.end(), ck.begin());
   unsigned long long queue = 0;
+  const int budget = argc > 8 ? atoi(argv[8]) : 0;
+  std::vector<double> wst(4 * (size_t)n, 0.0);
+  std::vector<int> order(n, 0);
+  std::vector<unsigned int> sched(2 + 2 * CHEM_SCHED_BINS, 0u);
   emu::run_grid(1, [&] {
-    chem_k_ros2_persistent_rec(n, ld, y.data(), lnA.data(), o, status.data(), counters.data(), &queue, nullptr, 0, 0,
-                               nullptr, nullptr, nullptr, hs.data(), tacc.data(), cap);
+    chem_k_ros2_persistent_rec(n, ld, y.data(), lnA.data(), o, status.data(), counters.data(), &queue, nullptr, 0,
+                               budget, budget > 0 ? wst.data() : nullptr, nullptr, budget > 0 ? sched.data() : nullptr,
+                               hs.data(), tacc.data(), cap);
   }, block);
+  if (budget > 0) {
+    emu::run_grid(1, [&] { chem_k_sched_scan(sched.data()); }, CHEM_SCHED_BINS);
+    emu::run_grid((unsigned)((n + 255) / 256), [&] {
+      chem_k_sched_scatter(n, status.data(), wst.data(), sched.data(), order.data());
+    }, 256);
+    queue = 0;
+    emu::run_grid(1, [&] {
+      chem_k_ros2_persistent_rec(n, ld, y.data(), lnA.data(), o, status.data(), counters.data(), &queue, nullptr, 0,
+                                 0, wst.data(), order.data(), sched.data(), hs.data(), tacc.data(), cap);
+    }, block);
+  }
   // adjoint: one block, cells strided over its lanes; segment records [K][SEG_W][seg_ld]
   const long long seg_ld = block;
   std::vector<double> seg((size_t)K * (4 * NY + NY * NY) * seg_ld, 0.0), dLdy0((size_t)NY * ld, 0.0),
