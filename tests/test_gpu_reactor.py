@@ -163,6 +163,34 @@ def test_reactor_register_form(name, case):
         assert np.array_equal(g0[:, inert], y0[:, inert])
 
 
+def test_reactor_failure_statuses_register_form():
+    """Per-cell statuses in the reactor mode (full-system build): non-finite and T <= 0 input cells
+    (both forms, backward Euler and Rosenbrock), Newton failure without halving, the attempt budget."""
+    import paper_2510_10005_amd as P
+    from paper_2510_10005_amd import default_options
+    gm, om = gpu_mechanism("h2like_10_27")
+    T, p, Y = sample_config("be_small", om.ns, 6)
+    y0 = oracle.state_from_TPY(om, T, p, Y)
+    bad = y0.copy()
+    bad[0, 2] = np.nan
+    bad[1, 0] = -3.0
+    for method in (P.CHEM_BE, P.CHEM_ROS2):
+        for form in (P.CHEM_PERSISTENT, P.CHEM_PLAIN):
+            got, st, _ = _integrate_gpu(gm, bad, default_options(method=method, dt=1e-8, n_steps=1, form=form,
+                                                                 energy=REACTOR), 9)
+            assert st[0] == oracle.CELL_NONFINITE and st[1] == oracle.CELL_T_RANGE
+            np.testing.assert_array_equal(got[1], bad[1])
+            assert np.all(st[2:] == 0)
+    _, st, _ = _integrate_gpu(gm, y0, default_options(method=P.CHEM_BE, dt=1e-6, n_steps=1, newton_max=1,
+                                                      halving_max_depth=0, energy=REACTOR), 9)
+    assert np.all(st == oracle.CELL_NEWTON_FAIL)
+    _, st, cnt = _integrate_gpu(gm, y0, default_options(method=P.CHEM_ROS2, dt=1e-6, max_steps=3, energy=REACTOR), 9)
+    with np.errstate(all="ignore"):
+        ref = oracle.integrate_ros2(om, y0, 1e-6, opt=IntegratorOptions(max_steps=3, energy=REACTOR))
+    np.testing.assert_array_equal(st, ref["status"])
+    np.testing.assert_array_equal(cnt[0] + cnt[1], ref["accepted"] + ref["rejected"])
+
+
 def test_reactor_rosenbrock_launch_shape_larger_system():
     """The 12-species mechanism's reduced system (12 components) parks its U factor in 159,744 B of
     LDS at 256 threads per block; the full-system build (13) would need 186,368 B.  A launch shape
