@@ -425,11 +425,13 @@ bool known_energy(int e) { return e == CHEM_CONST_P || e == CHEM_CONST_V || e ==
 
 // The reactor form changes every concentration (the density follows T and the mole number), so it
 // needs integrators that solve the full system: the block form's (n > 24) and, for register-resident
-// mechanisms, those of the full-system build.  No tapes (the adjoints have no dilatation terms).
+// mechanisms, those of the full-system build.  Tapes: the block form's backward-Euler adjoint has
+// the dilatation terms; the register-form adjoints replay with the reduced system and do not.
 chem_err check_reactor(const chem_mech* M, const chem_integrator_opts* o, bool tape) {
-  (void)M;
   if (o->energy != CHEM_CONST_P_REACTOR) return CHEM_OK;
-  if (tape) return fail(CHEM_EUNSUPPORTED, "no adjoint tape for the constant-pressure reactor form");
+  if (tape && !(M->wave && o->method == CHEM_BE))
+    return fail(CHEM_EUNSUPPORTED, "in the constant-pressure reactor form only the backward-Euler adjoint of "
+                "mechanisms with n > 24 records a tape");
   return CHEM_OK;
 }
 

@@ -4,7 +4,7 @@
 //   block_driver be|ros2|ros2p n ld dt n_steps in.bin out.bin [grid] [lu_strategy]
 //     (ros2p: probe/resume schedule; lu_strategy 1: the LDS-panel kernels, be and ros2 only)
 //     in.bin: state [NY][ld] then ln A [NR]; out.bin: state, status [ld], counters [3][ld]
-//   block_driver adj n ld dt n_steps K in.bin out.bin [grid]   (backward Euler with a tape, then its adjoint)
+//   block_driver adj n ld dt n_steps K in.bin out.bin [grid] [energy]   (backward Euler with a tape, then its adjoint)
 //     in.bin: state [NY][ld], ln A [NR], dL/dy_N [NY][ld]; out.bin: state, status [ld], dL/dy0 [NY][ld],
 //     dL/dlnA [NR] (workgroup partials summed in workgroup order)
 //   block_driver src|jac n ld in.bin out.bin          (API kernels of mechanisms with n > 64)
@@ -117,7 +117,7 @@ int main(int argc, char** argv) {
     ChemOpts o{};
     o.dt = dt; o.rtol = 1e-6; o.atol = 1e-10; o.h_min = 1e-20; o.newton_rtol = 1e-10; o.newton_atol_T = 1e-8;
     o.newton_atol_Y = 1e-14; o.n_steps = n_steps; o.max_steps = 100000; o.newton_max = 10;
-    o.halving_max_depth = 8; o.energy = 0; o.ckpt_every = K;
+    o.halving_max_depth = 8; o.energy = argc > 10 ? atoi(argv[10]) : 0; o.ckpt_every = K;
     emu::run_grid(grid, [&] {
       chem_k_be_persistent(n, ld, y.data(), lnA.data(), o, status.data(), counters.data(), &queue, ws.data(), 0,
                            ckpt.data(), nsub.data());

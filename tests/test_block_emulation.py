@@ -222,9 +222,11 @@ def test_block_rosenbrock_150_species(generator, tmp_path_factory):
     assert integrated_state_error(om, y, ref["y"]).max() <= 1e-8
 
 
-@pytest.mark.parametrize("name,step,nc,cfg", [("ch4like_53_325", 1e-6, 3, "be_small"), ("mix_30_90", 1e-3, 3, "be_small"),
-                                              ("large_150_1000", 1e-11, 1, "ros2_large")])
-def test_block_be_adjoint_matches_oracle(generator, tmp_path_factory, name, step, nc, cfg):
+@pytest.mark.parametrize("name,step,nc,cfg,energy", [("ch4like_53_325", 1e-6, 3, "be_small", 0),
+                                                     ("mix_30_90", 1e-3, 3, "be_small", 0),
+                                                     ("large_150_1000", 1e-11, 1, "ros2_large", 0),
+                                                     ("mix_30_90", 1e-3, 3, "be_small", 2)])
+def test_block_be_adjoint_matches_oracle(generator, tmp_path_factory, name, step, nc, cfg, energy):
     """Backward Euler with a tape (checkpoints every 2 steps, 3 steps: for the two smaller mechanisms
     a halved step and a partial last segment), then the block-form discrete adjoint against the
     oracle's reverse sweep along the oracle's recorded (sub)steps; the 150-species mechanism keeps
@@ -238,7 +240,7 @@ def test_block_be_adjoint_matches_oracle(generator, tmp_path_factory, name, step
     if any(rx.kind == "plog" for rx in om.reactions):
         p = np.geomspace(2e4, 2e6, nc)
     y0 = oracle.state_from_TPY(om, T, p, Y)
-    ref = oracle.integrate_be(om, y0, dt, n_steps, record=True)
+    ref = oracle.integrate_be(om, y0, dt, n_steps, record=True, opt=IntegratorOptions(energy=energy))
     if om.ns < 100:
         assert max(len(t) for t in ref["trajectory"]) > n_steps  # at least one halved step
     _, lamN = final_loss(om, ref["y"], loss_weights(nc, om.ns))
@@ -249,7 +251,7 @@ def test_block_be_adjoint_matches_oracle(generator, tmp_path_factory, name, step
         f.write(ys.astype("<f8").tobytes())
         f.write(np.asarray(om.lnA_default, "<f8").tobytes())
         f.write(ls.astype("<f8").tobytes())
-    _run([exe, "adj", str(nc), str(ld), repr(dt), str(n_steps), str(K), fin, fout, str(grid)])
+    _run([exe, "adj", str(nc), str(ld), repr(dt), str(n_steps), str(K), fin, fout, str(grid), str(energy)])
     raw = open(fout, "rb").read()
     k = 8 * om.n * ld
     y = np.frombuffer(raw[:k], "<f8").reshape(om.n, ld)[:, :nc].T
@@ -258,7 +260,7 @@ def test_block_be_adjoint_matches_oracle(generator, tmp_path_factory, name, step
     g = np.frombuffer(raw[2 * k + 4 * ld:], "<f8")
     np.testing.assert_array_equal(st, ref["status"])
     assert integrated_state_error(om, y, ref["y"]).max() <= 1e-8
-    lam0_ref, g_ref = be_adjoint(om, lamN, ref["trajectory"])
+    lam0_ref, g_ref = be_adjoint(om, lamN, ref["trajectory"], energy=energy)
     scale = np.abs(lam0_ref).max(axis=0, keepdims=True)
     assert (np.abs(lam0 - lam0_ref) / np.where(scale > 0, scale, 1.0)).max() <= 1e-6
     gs = g_ref.sum(axis=0)

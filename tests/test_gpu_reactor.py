@@ -9,8 +9,10 @@
   species in the solved system): backward Euler (persistent and plain), Rosenbrock (persistent and
   plain), SDIRK-2, SDIRK-4 and YASS with LU against the oracle on the same bar, and the regular
   build keeps running the other modes in the same process;
-* the host refuses the reactor form for adjoint tapes and unknown energy modes before any kernel
-  runs.
+* the block form's backward-Euler discrete adjoint in the reactor mode (dilatation terms in the
+  transposed Jacobian and in the ln A contraction) against the oracle's adjoint, 1e-6 element-wise;
+* the host refuses the reactor form for the other adjoint tapes and unknown energy modes before any
+  kernel runs.
 """
 
 import numpy as np
@@ -240,6 +242,51 @@ def test_reactor_autotune_register_form():
     assert integrated_state_error(om, got[idx], ref["y"]).max() <= 1e-8
 
 
+def test_reactor_be_adjoint_block_form(block_mech):
+    import torch
+    from oracle.sensitivity import be_adjoint, final_loss
+    from paper_2510_10005_amd import CHEM_BE, Tape, default_options
+    from synth.states import loss_weights
+    from _gpu import gradient_errors
+    gm, om = block_mech
+    nc, dt, n_steps, K = 8, 6e-8, 6, 4
+    T, p, Y = sample_config("be_small", om.ns, nc)
+    y0 = oracle.state_from_TPY(om, T, p, Y)
+    ref = oracle.integrate_be(om, y0, dt, n_steps, record=True, opt=IntegratorOptions(energy=REACTOR))
+    assert np.all(ref["status"] == 0)
+    _, lamN = final_loss(om, ref["y"], loss_weights(nc, om.ns))
+    lam0_ref, g_ref = be_adjoint(om, lamN, ref["trajectory"], energy=REACTOR)
+    tape = Tape(gm, nc, K)
+    print(f"[gpu] reactor BE adjoint n={om.n}", flush=True)
+    got, st, _ = _integrate_gpu_tape(gm, y0, default_options(method=CHEM_BE, dt=dt, n_steps=n_steps, energy=REACTOR),
+                                     nc, tape)
+    np.testing.assert_array_equal(st, ref["status"])
+    assert integrated_state_error(om, got, ref["y"]).max() <= 1e-8
+    out = empty(om.n, nc)
+    g = torch.zeros(om.nr, dtype=torch.float64, device="cuda")
+    gm.chem_integrate_adjoint(tape, None, dev_soa(lamN), out, g)
+    torch.cuda.synchronize()
+    e0, el0 = gradient_errors(host_aos(out, nc), lam0_ref)
+    eg, elg = gradient_errors(g.cpu().numpy()[None, :], g_ref.sum(axis=0)[None, :])
+    print(f"[gpu] reactor BE adjoint: dL/dy0 {e0:.2e} (element-wise {el0:.2e}), dL/dlnA {eg:.2e} "
+          f"(element-wise {elg:.2e})", flush=True)
+    assert max(e0, el0, eg, elg) <= 1e-6
+    # the density-holding adjoint differs (the dilatation terms matter here)
+    lam0_held, _ = be_adjoint(om, lamN, ref["trajectory"])
+    assert gradient_errors(host_aos(out, nc), lam0_held)[0] > 1e-6
+
+
+def _integrate_gpu_tape(gm, y0, opts, ld, tape):
+    import torch
+    nc = y0.shape[0]
+    y = dev_soa(y0, ld)
+    status = torch.full((ld,), -7, dtype=torch.int32, device="cuda")
+    counters = torch.zeros((3, ld), dtype=torch.int32, device="cuda")
+    gm.chem_integrate(nc, ld, y, None, opts, tape, status, counters)
+    torch.cuda.synchronize()
+    return host_aos(y, nc), status.cpu().numpy()[:nc], counters.cpu().numpy()[:, :nc]
+
+
 def test_reactor_api_kernels_150_species():
     import torch
     gm, om = gpu_mechanism("large_150_1000")
@@ -282,7 +329,7 @@ def test_reactor_refusals():
     big, om_b = gpu_mechanism("mix_30_90")
     yb = torch.zeros((om_b.n, 8), dtype=torch.float64, device="cuda")
     with pytest.raises(ChemError, match="tape"):
-        big.chem_integrate(8, 8, yb, None, default_options(method=CHEM_BE, dt=1e-8, n_steps=1, energy=REACTOR),
+        big.chem_integrate(8, 8, yb, None, default_options(method=CHEM_ROS2, dt=1e-8, energy=REACTOR),
                            Tape(big, 8, 1), st, None)
     with pytest.raises(ChemError, match="energy"):
         big.chem_integrate(8, 8, yb, None, default_options(method=CHEM_BE, dt=1e-8, n_steps=1, energy=3), None, st,

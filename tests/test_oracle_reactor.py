@@ -200,3 +200,32 @@ def test_temperature_from_enthalpy_as_constant_pressure(mech_small):
     T0 = y[:, 0] * 0.9
     np.testing.assert_array_equal(oracle.T_from_energy(m, y[:, 1:], e, T0, CONST_P_REACTOR),
                                   oracle.T_from_energy(m, y[:, 1:], e, T0, CONST_P))
+
+
+def test_backward_euler_sensitivities_in_reactor_mode(mech_tiny):
+    """The backward-Euler tangent in the reactor mode against central differences of the forward
+    map in ln A (three reactions), and the adjoint against the tangent (dot-product identity)."""
+    from oracle.sensitivity import be_adjoint, be_tangent, final_loss
+    from synth.states import loss_weights
+    m = mech_tiny
+    T, p, Y = sample_config("be_small", m.ns, 3)
+    y0 = oracle.state_from_TPY(m, T, p, Y)
+    opt = IntegratorOptions(energy=CONST_P_REACTOR)
+    fwd = lambda lnA: oracle.integrate_be(m, y0, 1e-7, 12, lnA=lnA, opt=opt, record=True)  # noqa: E731
+    r = fwd(None)
+    assert np.all(r["status"] == 0)
+    s = be_tangent(m, y0, r["trajectory"], energy=CONST_P_REACTOR)
+    h = 1e-6
+    for j in (0, m.nr // 2, m.nr - 1):
+        lp, lm = m.lnA_default.copy(), m.lnA_default.copy()
+        lp[j] += h
+        lm[j] -= h
+        fd = (fwd(lp)["y"] - fwd(lm)["y"]) / (2 * h)
+        scale = np.abs(s[:, :, j]).max(axis=1, keepdims=True)
+        noise = 1e-15 * np.abs(r["y"]) / h
+        assert np.all(np.abs(fd - s[:, :, j]) <= 1e-5 * scale + noise), j
+    _, lam = final_loss(m, r["y"], loss_weights(3, m.ns))
+    lam0, g = be_adjoint(m, lam, r["trajectory"], energy=CONST_P_REACTOR)
+    via_tangent = np.einsum("ci,cik->ck", lam, s)
+    np.testing.assert_allclose(g, via_tangent[:, :m.nr], rtol=1e-9, atol=1e-12 * np.abs(g).max())
+    np.testing.assert_allclose(lam0, via_tangent[:, m.nr:], rtol=1e-9, atol=1e-12 * np.abs(lam0).max())
