@@ -109,8 +109,8 @@ enum { CHEM_FLAG_CHECK_CELLS = 1 };  /* synchronise and return CHEM_ECELLS if a 
  *           CHEM_CONST_V: omega_T = -sum U_i omega_i / sum C_i Cv_i (Section 3)
  *           CHEM_CONST_P_REACTOR: the constant-pressure reactor with its density change (the
  *           omega_T of CHEM_CONST_P, species sources omega_i - C_i g; see chem_source_terms).
- *           Every method and form; tapes for the backward-Euler adjoint of mechanisms with
- *           n > 24 only (CHEM_EUNSUPPORTED otherwise).  Its expansion changes
+ *           Every method and form; adjoint tapes for backward Euler only (CHEM_EUNSUPPORTED for a
+ *           Rosenbrock tape).  Its expansion changes
  *           every concentration, so for n <= 24 the integrators run a second build of the
  *           mechanism whose solved system holds every species (the regular one holds the species
  *           that take part in no reaction fixed); it is generated, compiled (or taken from the

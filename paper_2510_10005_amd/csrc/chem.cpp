@@ -205,15 +205,15 @@ void build_one(const std::string& src, const std::string& arch, const std::strin
 
 // generate + compile (or fetch from the cache) the code objects of a mechanism: one entry for a
 // register-resident mechanism, kGroups entries otherwise.  full_system (register-resident
-// mechanisms): the build whose integrators solve for every species, groups 1 (Rosenbrock) and 2
-// (backward Euler, SDIRK, YASS) only.
+// mechanisms): the build whose integrators solve for every species, groups 1 (Rosenbrock), 2
+// (backward Euler, SDIRK, YASS) and 3 (adjoints) only.
 chem_err build_code_objects(const chem::Mechanism& m, const std::string& arch, const std::string& cache_dir,
                             std::vector<CodeObject>& objs, bool full_system = false) {
   const std::string src = chem::generate_source(m, kDenseLimit, full_system);
   const bool split = m.n() > kDenseLimit;
   std::vector<int> groups;
   if (full_system)
-    groups = {1, 2};
+    groups = {1, 2, 3};
   else if (split)
     for (int g = 0; g < kGroups; ++g) groups.push_back(g);
   else
@@ -425,13 +425,15 @@ bool known_energy(int e) { return e == CHEM_CONST_P || e == CHEM_CONST_V || e ==
 
 // The reactor form changes every concentration (the density follows T and the mole number), so it
 // needs integrators that solve the full system: the block form's (n > 24) and, for register-resident
-// mechanisms, those of the full-system build.  Tapes: the block form's backward-Euler adjoint has
-// the dilatation terms; the register-form adjoints replay with the reduced system and do not.
+// mechanisms, those of the full-system build.  Tapes: the backward-Euler adjoints carry the
+// dilatation terms (block form; full-system build of the register form); the Rosenbrock adjoint's
+// vector-Jacobian products do not.
 chem_err check_reactor(const chem_mech* M, const chem_integrator_opts* o, bool tape) {
+  (void)M;
   if (o->energy != CHEM_CONST_P_REACTOR) return CHEM_OK;
-  if (tape && !(M->wave && o->method == CHEM_BE))
-    return fail(CHEM_EUNSUPPORTED, "in the constant-pressure reactor form only the backward-Euler adjoint of "
-                "mechanisms with n > 24 records a tape");
+  if (tape && o->method != CHEM_BE)
+    return fail(CHEM_EUNSUPPORTED, "in the constant-pressure reactor form only the backward-Euler adjoint "
+                "records a tape");
   return CHEM_OK;
 }
 
@@ -462,8 +464,8 @@ chem_err validate_opts(const chem_integrator_opts* o) {
   return CHEM_OK;
 }
 
-// the full-system build of a register-resident mechanism (groups 1 and 2: every integrator), once;
-// the kernels of the other groups come from the regular build.  Called under M->mu.
+// the full-system build of a register-resident mechanism (groups 1 to 3: every integrator and the
+// adjoints), once; the kernels of group 0 come from the regular build.  Called under M->mu.
 chem_err load_full_system(chem_mech* M) {
   if (M->full_loaded) return CHEM_OK;
   std::vector<CodeObject> objs;
@@ -476,7 +478,7 @@ chem_err load_full_system(chem_mech* M) {
   for (int k = 0; k < K_COUNT; ++k) {
     const int g = kKernelGroup[k];
     M->fn_full[k] = M->fn[k];
-    if ((g != 1 && g != 2) || lu_strategy_kernel(k)) continue;
+    if (g < 1 || g > 3 || lu_strategy_kernel(k)) continue;
     HIP_TRY(hipModuleGetFunction(&M->fn_full[k], M->modules_full[g - 1], kKernelNames[k]));
   }
   M->full_loaded = true;
@@ -1145,6 +1147,12 @@ chem_err chem_integrate_adjoint(const chem_mech* Mc, chem_tape* tape, const doub
     return fail(CHEM_EUNSUPPORTED, "mechanisms with n > 24 have the backward-Euler adjoint only");
   if (!tape->recorded) return fail(CHEM_EINVAL, "tape holds no recorded forward run");
   std::lock_guard<std::mutex> lock(M->mu);
+  // a tape recorded in the reactor mode of a register-resident mechanism is swept by the adjoint of
+  // the full-system build (its replays solve for every species)
+  const bool full = tape->opts.energy == CHEM_CONST_P_REACTOR && M->dense;
+  if (full)
+    if (chem_err e = load_full_system(M)) return e;
+  FullSystemScope scope(full);
   hipStream_t s = static_cast<hipStream_t>(stream);
   StreamFence fence(M, s);
   if (chem_err e = fence.begin()) return e;

@@ -832,6 +832,13 @@ std::string generate_source(const Mechanism& m, int dense_limit, bool full_syste
   os << "  const double off = energy == 1 ? 1.0 : 0.0;\n  double D = 0.0;\n"
         "#pragma unroll\n  for (int i = 0; i < NS; ++i) D = fma(C[i], cpR[i] - off, D);\n";
   os << "  const double muT = -T * mu[0] / D;\n";
+  if (full_system) {
+    // reactor mode (full-system build): d g / d lnA_j = q_j (sum_i nu_ij / sum C - dH_j / D) adds
+    // -(mu . C) times that to the contraction
+    os << "  double aC = 0.0, aH = 0.0;\n  if (energy == 2) {\n    double muC = 0.0, c = 0.0;\n"
+          "#pragma unroll\n    for (int i = 0; i < NS; ++i) {\n      muC = fma(mu[1 + i], C[i], muC);\n"
+          "      c += C[i];\n    }\n    aC = muC / c;\n    aH = muC / D;\n  }\n";
+  }
   for (int j = 0; j < nr; ++j) {
     emit_rate(os, m, j, false, red);
     auto nu = m.net(j);
@@ -851,7 +858,13 @@ std::string generate_source(const Mechanism& m, int dense_limit, bool full_syste
       os << num(static_cast<double>(p.second)) << "*mu[" << 1 + p.first << "]";
     }
     if (first) os << "0.0";
-    os << ";\n    g[" << j << "] += q * (sm + muT * dH);\n  }\n";
+    if (full_system) {
+      int dnu = 0;
+      for (auto& p : nu) dnu += p.second;
+      os << ";\n    g[" << j << "] += q * (fma(-aC, " << num(static_cast<double>(dnu)) << ", sm) + (muT + aH) * dH);\n  }\n";
+    } else {
+      os << ";\n    g[" << j << "] += q * (sm + muT * dH);\n  }\n";
+    }
   }
   os << "}\n";
   // ---- NASA-7 values for a generic value type (plain or dual numbers); the range is chosen by

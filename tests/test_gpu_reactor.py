@@ -9,8 +9,9 @@
   species in the solved system): backward Euler (persistent and plain), Rosenbrock (persistent and
   plain), SDIRK-2, SDIRK-4 and YASS with LU against the oracle on the same bar, and the regular
   build keeps running the other modes in the same process;
-* the block form's backward-Euler discrete adjoint in the reactor mode (dilatation terms in the
-  transposed Jacobian and in the ln A contraction) against the oracle's adjoint, 1e-6 element-wise;
+* the backward-Euler discrete adjoint in the reactor mode (dilatation terms in the transposed
+  Jacobian and in the ln A contraction), block form and the register form's full-system build,
+  against the oracle's adjoint, 1e-6 element-wise;
 * the host refuses the reactor form for the other adjoint tapes and unknown energy modes before any
   kernel runs.
 """
@@ -243,13 +244,23 @@ def test_reactor_autotune_register_form():
 
 
 def test_reactor_be_adjoint_block_form(block_mech):
+    _reactor_be_adjoint(*block_mech, 8)
+
+
+@pytest.mark.parametrize("name", ["tiny_8_14", "h2like_10_27"])
+def test_reactor_be_adjoint_register_form(name):
+    """The register form's backward-Euler adjoint in the reactor mode: the full-system build's
+    adjoint kernel (replays on the full system, dilatation terms in the ln A contraction)."""
+    _reactor_be_adjoint(*gpu_mechanism(name), 70)
+
+
+def _reactor_be_adjoint(gm, om, nc):
     import torch
     from oracle.sensitivity import be_adjoint, final_loss
     from paper_2510_10005_amd import CHEM_BE, Tape, default_options
     from synth.states import loss_weights
     from _gpu import gradient_errors
-    gm, om = block_mech
-    nc, dt, n_steps, K = 8, 6e-8, 6, 4
+    dt, n_steps, K = 6e-8, 6, 4
     T, p, Y = sample_config("be_small", om.ns, nc)
     y0 = oracle.state_from_TPY(om, T, p, Y)
     ref = oracle.integrate_be(om, y0, dt, n_steps, record=True, opt=IntegratorOptions(energy=REACTOR))
@@ -257,7 +268,7 @@ def test_reactor_be_adjoint_block_form(block_mech):
     _, lamN = final_loss(om, ref["y"], loss_weights(nc, om.ns))
     lam0_ref, g_ref = be_adjoint(om, lamN, ref["trajectory"], energy=REACTOR)
     tape = Tape(gm, nc, K)
-    print(f"[gpu] reactor BE adjoint n={om.n}", flush=True)
+    print(f"[gpu] reactor BE adjoint n={om.n}, {nc} cells", flush=True)
     got, st, _ = _integrate_gpu_tape(gm, y0, default_options(method=CHEM_BE, dt=dt, n_steps=n_steps, energy=REACTOR),
                                      nc, tape)
     np.testing.assert_array_equal(st, ref["status"])
@@ -320,9 +331,6 @@ def test_reactor_refusals():
     small, om_s = gpu_mechanism("h2like_10_27")
     y = torch.zeros((om_s.n, 8), dtype=torch.float64, device="cuda")
     st = torch.zeros(8, dtype=torch.int32, device="cuda")
-    with pytest.raises(ChemError, match="tape"):
-        small.chem_integrate(8, 8, y, None, default_options(method=CHEM_BE, dt=1e-8, n_steps=1, energy=REACTOR),
-                             Tape(small, 8, 1), st, None)
     with pytest.raises(ChemError, match="tape"):
         small.chem_integrate(8, 8, y, None, default_options(method=CHEM_ROS2, dt=1e-8, energy=REACTOR),
                              Tape(small, 8, 1, method=CHEM_ROS2, max_steps=16), st, None)
