@@ -25,8 +25,9 @@ under ulp perturbations.)
 
 Cases: the backward-Euler workload's states at the paper's YASS step (1e-7 s, Table 5) and at
 2 x 1e-6 s (substep halving active) in both energy modes, a tighter alpha, GMRES with Jacobi
-preconditioning (both energy modes, a tighter alpha, restarted GMRES(4)), with Gauss-Seidel
-preconditioning (both energy modes) and without, the Rosenbrock
+preconditioning (constant pressure with the density held, constant volume, the constant-pressure
+reactor, a tighter alpha, restarted GMRES(4)), with Gauss-Seidel preconditioning (the same three
+energy modes) and without, the Rosenbrock
 workload's hot states, the h_min failure and the attempt budget, argument errors, and sampled
 cells of the 1024-cell workload over its 2e-5 s at the paper's step with the autotuned launch.
 """
@@ -124,6 +125,8 @@ CASES = {
     "gmres_no_precond": ("be_small", 150, 2e-6, 2, 0, dict(linear_solver=1, krylov_precond=0)),
     "gmres_gauss_seidel": ("be_small", 150, 2e-6, 2, 0, dict(linear_solver=1, krylov_precond=2)),
     "gmres_gauss_seidel_cv": ("be_small", 150, 2e-6, 2, 1, dict(linear_solver=1, krylov_precond=2)),
+    "gmres_jacobi_reactor": ("be_small", 150, 2e-6, 2, 2, dict(linear_solver=1)),
+    "gmres_gauss_seidel_reactor": ("be_small", 150, 2e-6, 2, 2, dict(linear_solver=1, krylov_precond=2)),
     "hot_states": ("ros2_1m", 150, 1e-7, 5, 0, {}),
 }
 
