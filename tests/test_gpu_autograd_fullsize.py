@@ -3,7 +3,8 @@ sampled parity of the benchmark workloads in the benchmark's launch configuratio
 
 * ChemIntegrate (BE forward + discrete adjoint) vs the oracle's discrete adjoint composed with
   its loss and init-map pull-backs: relative 1e-6 on dL/dlnA, dL/dT0, dL/dY0; plus central
-  differences (h = 1e-6) of the GPU forward on sampled ln A_j (the adjoint workload's check).
+  differences (h = 1e-6) of the GPU forward on sampled ln A_j (the adjoint workload's check); with
+  the density held (Appendix B) and in the constant-pressure reactor mode.
 * 1,048,576-cell Rosenbrock workload (persistent, autotuned launch): sampled cells vs the oracle
   one by one, relative 1e-8 where the step sequences agree.
 * 1024-cell backward-Euler workload (200 x 1e-7 s): sampled cells vs the oracle, relative 1e-8.
@@ -14,6 +15,7 @@ import pytest
 import torch
 
 import oracle
+from oracle.integrate import IntegratorOptions
 from oracle.sensitivity import be_adjoint, final_loss, init_map_vjp
 from synth.states import STATE_CONFIGS, loss_weights, sample_config, sample_states
 
@@ -27,7 +29,8 @@ def small():
     return gpu_mechanism("h2like_10_27")
 
 
-def test_autograd_matches_oracle_adjoint_and_fd(small):
+@pytest.mark.parametrize("energy", [0, 2])
+def test_autograd_matches_oracle_adjoint_and_fd(small, energy):
     from paper_2510_10005_amd.autograd import chem_integrate
     gm, om = small
     nc, dt, nst = 48, 4e-7, 20
@@ -37,15 +40,16 @@ def test_autograd_matches_oracle_adjoint_and_fd(small):
     T0 = d(T).requires_grad_(True)
     Y0 = d(Y.T).requires_grad_(True)
     lnA = d(om.lnA_default).requires_grad_(True)
-    TN, YN, st = chem_integrate(T0, Y0, lnA, gm, d(p), dt, nst, checkpoint_every=6)
+    print(f"[gpu] autograd, energy mode {energy}", flush=True)
+    TN, YN, st = chem_integrate(T0, Y0, lnA, gm, d(p), dt, nst, checkpoint_every=6, energy=energy)
     L = TN.sum() + (d(w.T) * YN).sum()
     L.backward()
     assert torch.all(st == 0)
     # oracle: forward with trajectory, loss pull-back, adjoint, init-map pull-back
     y0 = oracle.state_from_TPY(om, T, p, Y)
-    ref = oracle.integrate_be(om, y0, dt, nst, record=True)
+    ref = oracle.integrate_be(om, y0, dt, nst, record=True, opt=IntegratorOptions(energy=energy))
     _, lamN = final_loss(om, ref["y"], w)
-    lam0, g = be_adjoint(om, lamN, ref["trajectory"])
+    lam0, g = be_adjoint(om, lamN, ref["trajectory"], energy=energy)
     dT_ref, dY_ref = init_map_vjp(om, T, p, Y, lam0)
     g_ref = g.sum(axis=0)
 
@@ -65,7 +69,7 @@ def test_autograd_matches_oracle_adjoint_and_fd(small):
             la = lnA.detach().clone()
             la[j] += s * h
             with torch.no_grad():
-                TN2, YN2, _ = chem_integrate(T0.detach(), Y0.detach(), la, gm, d(p), dt, nst)
+                TN2, YN2, _ = chem_integrate(T0.detach(), Y0.detach(), la, gm, d(p), dt, nst, energy=energy)
                 vals.append(float(TN2.sum() + (d(w.T) * YN2).sum()))
         fd = (vals[0] - vals[1]) / (2 * h)
         noise = 4e-16 * abs(float(L)) / h
